@@ -1,0 +1,449 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle by a route other than its own code: a closed
+form, a textbook or library routine, brute force on tiny inputs, an identity
+stated in the paper, or a value the paper prints (tests/golden).  Together
+they are chosen so that a dropped term, a wrong sign or index, or a
+transposed operand anywhere in the oracle fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import epic_oracle as O
+from paper_1603_02126_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(1234)
+
+
+def crandn(*shape, rng=RNG):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)
+
+
+# ---------------------------------------------------------------------------
+# input decoding
+# ---------------------------------------------------------------------------
+
+def test_unpack_ci4_exhaustive():
+    codes = np.arange(256, dtype=np.uint8)
+    got = O.unpack(codes, O.FMT_CI4)
+    # independent route: arithmetic shifts of the byte as a signed int8
+    s = codes.view(np.int8).astype(np.int64)
+    re = s >> 4
+    im = ((s << 4) & 0xFF).astype(np.uint8).view(np.int8).astype(np.int64) >> 4
+    assert np.array_equal(got.real, re) and np.array_equal(got.imag, im)
+    # spot values written out by hand
+    assert O.unpack(np.uint8(0x80), O.FMT_CI4) == complex(-8, 0)
+    assert O.unpack(np.uint8(0x7F), O.FMT_CI4) == complex(7, -1)
+    assert O.unpack(np.uint8(0x0F), O.FMT_CI4) == complex(0, -1)
+    assert O.unpack(np.uint8(0xF8), O.FMT_CI4) == complex(-1, -8)
+    assert O.unpack(np.uint8(0x17), O.FMT_CI4) == complex(1, 7)
+
+
+def test_unpack_ci8_exhaustive():
+    v = np.arange(-128, 128, dtype=np.int64)
+    re, im = np.meshgrid(v, v, indexing="ij")
+    packed = np.stack([re, im], axis=-1).astype(np.int8)
+    got = O.unpack(packed, O.FMT_CI8)
+    assert np.array_equal(got.real, re) and np.array_equal(got.imag, im)
+
+
+def test_generator_packing_roundtrip():
+    v = np.arange(-8, 8)
+    re, im = np.meshgrid(v, v, indexing="ij")
+    b = synth.pack_ci4(re.astype(np.int8), im.astype(np.int8))
+    got = O.unpack(b, O.FMT_CI4)
+    assert np.array_equal(got.real, re) and np.array_equal(got.imag, im)
+    assert len(np.unique(b)) == 256
+
+
+# ---------------------------------------------------------------------------
+# plan: gridding kernel, pixels, response, model
+# ---------------------------------------------------------------------------
+
+def test_nearest_cells_by_hand():
+    xy = np.array([[2.5 * 0.5, 0.0], [2.49 * 0.5, 0.0], [-0.25, 31.6 * 0.5], [-0.3, 0.74]])
+    c = O.grid_cells(xy, 0.5, 0.5, 0.0, 0.0, 32, 32, 1)
+    # p = 2.5 -> 3 (half up), 2.49 -> 2, -0.5 -> 0, -0.6 -> -1 -> 31 (wrap), 31.6 -> 32 -> 0
+    assert c.ix[:, 0].tolist() == [3, 2, 0, 31]
+    assert c.iy[:, 0].tolist() == [0, 0, 0, 1]
+    assert np.all(c.w == 1.0)
+
+
+def test_bilinear_cells_by_hand():
+    c = O.grid_cells(np.array([[1.25 * 2.0 + 10.0, 2.5 * 2.0 - 4.0]]), 2.0, 2.0, 10.0, -4.0, 16, 16, 2)
+    assert c.ix[0].tolist() == [1, 2, 1, 2]
+    assert c.iy[0].tolist() == [2, 2, 3, 3]
+    np.testing.assert_allclose(c.w[0], [0.75 * 0.5, 0.25 * 0.5, 0.75 * 0.5, 0.25 * 0.5], rtol=0, atol=1e-15)
+
+
+def test_bilinear_preserves_mass_and_centroid():
+    # area overlap of a one-cell tophat: weights sum to one and their
+    # weighted cell position is the antenna position (no wrap)
+    xy = RNG.uniform(5.0, 40.0, size=(200, 2))
+    c = O.grid_cells(xy, 1.0, 1.0, 0.0, 0.0, 64, 64, 2)
+    np.testing.assert_allclose(c.w.sum(1), 1.0, atol=1e-14)
+    np.testing.assert_allclose((c.w * c.ix).sum(1), xy[:, 0], atol=1e-12)
+    np.testing.assert_allclose((c.w * c.iy).sum(1), xy[:, 1], atol=1e-12)
+    assert np.all(c.w >= 0)
+
+
+def test_pixel_of_direction():
+    c = O.C_LIGHT
+    # N d f / c = 16 wavelengths: pixel kappa at l = kappa / 16
+    assert O.pixel_of_direction(0.0, 0.0, c, 32, 32, 0.5, 0.5) == (0, 0)
+    assert O.pixel_of_direction(1 / 16, -3 / 16, c, 32, 32, 0.5, 0.5) == (1, 29)
+    assert O.pixel_of_direction(0.5 / 16, -0.5 / 16, c, 32, 32, 0.5, 0.5) == (1, 0)   # ties round up
+    assert O.pixel_of_direction(0.49 / 16, -0.51 / 16, c, 32, 32, 0.5, 0.5) == (0, 31)
+    l, m = O.direction_of_pixel(1, 29, c, 32, 32, 0.5, 0.5)
+    assert abs(l - 1 / 16) < 1e-15 and abs(m + 3 / 16) < 1e-15
+
+
+def test_pixel_response():
+    xy = RNG.uniform(0.0, 30.0, size=(20, 2))
+    c = O.grid_cells(xy, 1.0, 1.0, 0.0, 0.0, 32, 32, 2)
+    np.testing.assert_allclose(O.pixel_response(c, 0, 0, 32, 32), 1.0, atol=1e-14)
+    # a single cell at (jx, jy) = (3, 5) seen from pixel (2, 7): exp(2 pi i (6/32 + 35/32))
+    one = O.GridCells(ix=np.array([[3]]), iy=np.array([[5]]), w=np.array([[1.0]]))
+    want = np.cos(2 * np.pi * 41 / 32) + 1j * np.sin(2 * np.pi * 41 / 32)
+    assert abs(O.pixel_response(one, 2, 7, 32, 32)[0] - want) < 1e-14
+
+
+def test_model_visibilities():
+    xy = RNG.uniform(-20, 20, size=(7, 2))
+    f = 60e6
+    V = O.model_visibilities(xy, f, np.array([[0.0, 0.0, 3.0]]))
+    np.testing.assert_allclose(V, 3.0, atol=1e-14)
+    src = np.array([[0.1, -0.2, 2.0], [0.3, 0.05, 1.5]])
+    V = O.model_visibilities(xy, f, src)
+    np.testing.assert_allclose(V, V.conj().T, atol=1e-14)
+    np.testing.assert_allclose(np.diag(V), 3.5, atol=1e-14)
+    a, b = 2, 5
+    want = sum(S * np.exp(-2j * np.pi * f * ((xy[a] - xy[b]) @ np.array([l, m])) / O.C_LIGHT)
+               for l, m, S in src)
+    assert abs(V[a, b] - want) < 1e-12
+
+
+def test_denominator_closed_form_and_factorised():
+    Na = 9
+    xy = RNG.uniform(-20, 20, size=(Na, 2))
+    # single zenith source, nearest cells, tapped pixel 0: A = 1, D_a = (Na - 1) S
+    A = np.ones(Na, complex)
+    V = O.model_visibilities(xy, 50e6, np.array([[0.0, 0.0, 4.0]]))
+    np.testing.assert_allclose(O.denominator(A, V), (Na - 1) * 4.0, atol=1e-13)
+    flags = np.zeros(Na, np.uint8)
+    flags[[1, 4]] = 1
+    D = O.denominator(A, V, flags)
+    want = np.where(flags == 0, (Na - 3) * 4.0, (Na - 2) * 4.0)
+    np.testing.assert_allclose(D, want, atol=1e-13)
+    # general: factor V^M over sources (a route the oracle does not take)
+    src = np.array([[0.1, -0.2, 2.0], [0.3, 0.05, 1.5], [-0.4, 0.4, 0.7]])
+    A = crandn(Na)
+    V = O.model_visibilities(xy, 50e6, src)
+    e = np.exp(-2j * np.pi * 50e6 * (xy @ src[:, :2].T) / O.C_LIGHT)       # [Na, Ns]
+    ok = flags == 0
+    B = (np.conj(A)[ok, None] * np.conj(e[ok])).sum(0)
+    Df = (src[:, 2][None] * e * B[None]).sum(1) - np.where(ok, np.conj(A) * src[:, 2].sum(), 0)
+    np.testing.assert_allclose(O.denominator(A, V, flags), Df, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# transform
+# ---------------------------------------------------------------------------
+
+def test_dft_bruteforce_and_numpy():
+    ny, nx, na = 4, 8, 3.0
+    G = crandn(2, ny, nx)
+    X = O.dft2(G, na)
+    B = np.zeros_like(G)
+    for t in range(2):
+        for ky in range(ny):
+            for kx in range(nx):
+                s = 0
+                for jy in range(ny):
+                    for jx in range(nx):
+                        s += G[t, jy, jx] * np.exp(2j * np.pi * (jx * kx / nx + jy * ky / ny))
+                B[t, ky, kx] = s / na
+    np.testing.assert_allclose(X, B, rtol=0, atol=1e-12)
+    G = crandn(3, 32, 32)
+    np.testing.assert_allclose(O.dft2(G, 7.0), np.fft.ifft2(G) * (32 * 32) / 7.0, atol=1e-11)
+    np.testing.assert_allclose(O.dft2(G, 7.0, sign=-1), np.fft.fft2(G) / 7.0, atol=1e-11)
+
+
+def test_parseval():
+    G = crandn(5, 16, 16)
+    na = 11.0
+    X = O.dft2(G, na)
+    np.testing.assert_allclose((np.abs(X) ** 2).sum((1, 2)), (256 / na ** 2) * (np.abs(G) ** 2).sum((1, 2)),
+                               rtol=1e-12)
+
+
+def test_grid_bruteforce():
+    Na, N = 6, 8
+    xy = RNG.uniform(0, 8, size=(Na, 2))
+    c = O.grid_cells(xy, 1.0, 1.0, 0.0, 0.0, N, N, 2)
+    E = crandn(3, Na)
+    G = O.grid(E, c, N, N)
+    # dense route: each antenna's kernel as a full N x N weight image
+    W = np.zeros((Na, N, N))
+    for a in range(Na):
+        for k in range(4):
+            W[a, c.iy[a, k], c.ix[a, k]] += c.w[a, k]
+    np.testing.assert_allclose(G, np.einsum("ta,ayx->tyx", E, W), atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# identities of Sec. 2.2 (pins 4-6 of the test plan)
+# ---------------------------------------------------------------------------
+
+def _setup(seed=7, kernel=2, Na=14, N=16, cal=(0.12, -0.2)):
+    rng = np.random.default_rng(seed)
+    pb = O.Problem(ant_xy=rng.uniform(3, 20, size=(Na, 2)), freq_hz=np.array([70e6]), nx=N, ny=N,
+                   dx=1.5, dy=1.5, x0=0.0, y0=0.0, kernel=kernel,
+                   model_lmS=np.array([[cal[0], cal[1], 10.0], [-0.3, 0.1, 2.0]]),
+                   cal_lm=np.array(cal), gamma=0.3, t_cal=5)
+    return pb, O.channel_setup(pb, 0), rng
+
+
+def test_tap_is_beamformed_sum():
+    pb, s, rng = _setup()
+    E = crandn(5, 14, rng=rng)
+    g = crandn(14, rng=rng) + 2
+    X = O.dft2(O.grid(O.calibrate(E, g), s["cells"], 16, 16), s["na"])
+    kx, ky = s["k0"]
+    # beamformed sum with explicitly built phasors of each kernel cell
+    c = s["cells"]
+    A = np.array([sum(c.w[a, k] * np.exp(2j * np.pi * (c.ix[a, k] * kx + c.iy[a, k] * ky) / 16)
+                      for k in range(4)) for a in range(14)])
+    P = (E / g) @ A / 14
+    np.testing.assert_allclose(X[:, ky, kx], P, atol=1e-13)
+
+
+def test_C_identity_visibility_route():
+    """eq. (Cna): the K-route C equals (1/Na) sum_{b != a} conj(A_b)/conj(g_b) <E_a E_b*>."""
+    pb, s, rng = _setup()
+    T, Na = 40, 14
+    E = crandn(T, Na, rng=rng) * 3
+    g = crandn(Na, rng=rng) + 2
+    X = O.dft2(O.grid(O.calibrate(E, g), s["cells"], 16, 16), s["na"])
+    kx, ky = s["k0"]
+    K, Q = O.correlate(E, X[:, ky, kx])
+    A = s["A"]
+    C = K / T - np.conj(A) * (Q / T) / (Na * np.conj(g))
+    R = np.einsum("ta,tb->ab", E, np.conj(E)) / T
+    Cv = np.array([sum(np.conj(A[b]) / np.conj(g[b]) * R[a, b] for b in range(Na) if b != a) / Na
+                   for a in range(Na)])
+    np.testing.assert_allclose(C, Cv, rtol=1e-12, atol=1e-12)
+
+
+def test_image_identity():
+    """The EPIC image equals the gridded visibility image (Sec. 2.1 closing remark)."""
+    pb, s, rng = _setup(N=8, Na=6)
+    T, Na, N = 7, 6, 8
+    E = crandn(T, Na, rng=rng)
+    g = crandn(Na, rng=rng) + 2
+    Ec = O.calibrate(E, g)
+    X = O.dft2(O.grid(Ec, s["cells"], N, N), s["na"])
+    I = (np.abs(X) ** 2).mean(0)
+    R = np.einsum("ta,tb->ab", Ec, np.conj(Ec)) / T
+    Iv = np.zeros((N, N))
+    for ky in range(N):
+        for kx in range(N):
+            A = O.pixel_response(s["cells"], kx, ky, N, N)
+            Iv[ky, kx] = np.real(A @ R @ np.conj(A)) / Na ** 2
+    np.testing.assert_allclose(I, Iv, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the recursion (pins 1, 2, 7, 8, 9)
+# ---------------------------------------------------------------------------
+
+def _phase_ref(g, gt):
+    r = g / gt
+    return r / (r[..., :1] / np.abs(r[..., :1]))
+
+
+def test_noiseless_single_source_recovers_gains():
+    """Pin 1: constant-modulus point source at the phase centre, no noise,
+    unit initial gains, gamma = 0.5, update every sample: the gains are
+    recovered up to a global phase within 1e-10."""
+    wl = synth.config_tiny()
+    src = np.array([[0.0, 0.0, 100.0]])
+    wl = wl.replace(src_lmS=src, model_lmS=src, amp_model="constmod", noise=False)
+    E = synth.efield_channel(wl, 0)[:, None, :]
+    r = O.run(E, O.Problem.from_workload(wl), wl.g0)
+    err = np.abs(_phase_ref(r["gains"][-1, 0], wl.g_true[0]) - 1).max()
+    assert err < 1e-10, err
+    assert np.abs(_phase_ref(r["gains"][1, 0], wl.g_true[0]) - 1).max() > 0.1   # it really started far off
+
+
+def test_fixed_point_full_model_off_centre():
+    """Pin 2: exact gains, realised visibilities equal to the model (orthogonal
+    source tones over each interval), off-centre calibrator: one update
+    returns the gains unchanged."""
+    wl = synth.config_small(efmt=synth.FMT_CF32)
+    m = np.arange(1, wl.src_lmS.shape[0] + 1)
+    wl = wl.replace(amp_model="orthogonal", ortho_m=m, noise=False, model_lmS=wl.src_lmS,
+                    g0=wl.g_true.copy(), n_samples=wl.t_cal)
+    E = np.stack([synth.efield_channel(wl, c) for c in range(wl.array.n_chan)], axis=1)
+    r = O.run(E, O.Problem.from_workload(wl), wl.g0)
+    assert np.abs(r["gains"][-1] / wl.g_true - 1).max() < 1e-12
+
+
+def test_gamma_zero_and_single_source_limit():
+    """Pin 9: with gamma = 0 the damped update is eq. (cal_solution); for a
+    single zenith source it is the gain-weighted visibility sum
+    sum_{b != a} V_ab / conj(g_b) / ((Na - 1) S) of Sec. 2.2."""
+    Na, N, S = 10, 16, 7.0
+    rng = np.random.default_rng(3)
+    pb = O.Problem(ant_xy=rng.uniform(0, 15, size=(Na, 2)), freq_hz=np.array([O.C_LIGHT]), nx=N, ny=N,
+                   dx=1.0, dy=1.0, x0=0.0, y0=0.0, kernel=1, model_lmS=np.array([[0.0, 0.0, S]]),
+                   cal_lm=np.array([0.0, 0.0]), gamma=0.0, t_cal=30)
+    E = crandn(30, 1, Na, rng=rng) * 4
+    g0 = (crandn(1, Na, rng=rng) + 2)
+    r = O.run(E, pb, g0)
+    V = np.einsum("ta,tb->ab", E[:, 0], np.conj(E[:, 0])) / 30
+    want = np.array([sum(V[a, b] / np.conj(g0[0, b]) for b in range(Na) if b != a) / ((Na - 1) * S)
+                     for a in range(Na)])
+    np.testing.assert_allclose(r["gains"][1, 0], want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [0.35, 0.5, 0.7])
+def test_linearised_convergence_factors(gamma):
+    """Pin 7: around the single-source solution one damped update multiplies
+    a differential amplitude error by gamma + (1-gamma)/(Na-1), a
+    differential phase error by gamma - (1-gamma)/(Na-1), a common amplitude
+    error by 2 gamma - 1 and leaves a global phase unchanged (derived from
+    eq. damping)."""
+    Na, eps = 12, 1e-6
+    wl = synth.config_tiny().replace(n_samples=1, noise=False, amp_model="constmod", gamma=gamma,
+                                     src_lmS=np.array([[0.0, 0.0, 50.0]]), model_lmS=np.array([[0.0, 0.0, 50.0]]))
+    arr = wl.array
+    arr = synth.ArraySpec(ant_xy=arr.ant_xy[:Na], freq_hz=arr.freq_hz, nx=32, ny=32, dx=0.5, dy=0.5,
+                          x0=0.0, y0=0.0, kernel=1, efmt=synth.FMT_CF32)
+    gt = wl.g_true[:, :Na]
+    wl = wl.replace(array=arr, g_true=gt)
+    E = synth.efield_channel(wl, 0)[:, None, :]
+    pb = O.Problem.from_workload(wl)
+    zs = np.zeros(Na)
+    zs[0], zs[1] = 1.0, -1.0
+    modes = {"diff_amp": (zs, gamma + (1 - gamma) / (Na - 1)),
+             "diff_phase": (1j * zs, gamma - (1 - gamma) / (Na - 1)),
+             "common_amp": (np.ones(Na), 2 * gamma - 1),
+             "global_phase": (1j * np.ones(Na), 1.0)}
+    for name, (d, factor) in modes.items():
+        g0 = gt * (1 + eps * d)
+        g1 = O.run(E, pb, g0)["gains"][1, 0]
+        nz = d != 0
+        ratio = (g1[nz] / gt[0][nz] - 1) / (eps * d[nz])
+        np.testing.assert_allclose(ratio, factor, rtol=2e-5, atol=2e-5, err_msg=name)
+        np.testing.assert_allclose(g1[~nz] / gt[0][~nz] - 1, 0, atol=1e-11, err_msg=name)
+
+
+def test_effective_integration_time_golden():
+    """Pin 8: the damped update weights the undamped solution of k intervals
+    ago by (1 - gamma) gamma^k; the effective integration time
+    1 / sum w^2 = (1 + gamma) / (1 - gamma) matches the value printed in
+    Sec. 4 (eq. teff)."""
+    with open(os.path.join(GOLDEN, "teff.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        gamma = case["gamma"]
+        n = 400
+        # steady undamped solution 1 with a unit impulse in the first interval
+        g = np.ones(1, complex)
+        resp = []
+        for k in range(n):
+            Kbar = np.array([2.0 + 0j]) if k == 0 else np.array([1.0 + 0j])
+            g, _ = O.gain_update(Kbar, np.zeros(1), np.zeros(1, complex), np.array([1.0 + 0j]), g, 1.0, gamma)
+            resp.append(g[0].real - 1.0)
+        w = np.array(resp)
+        np.testing.assert_allclose(w.sum(), 1.0, atol=1e-12)
+        teff = 1.0 / np.sum(w ** 2)
+        np.testing.assert_allclose(teff, (1 + gamma) / (1 - gamma), rtol=1e-12)
+        assert round(teff, case["digits"]) == case["printed"]
+
+
+def test_origin_and_permutation_invariance():
+    """A whole-cell shift of the grid origin multiplies every pixel by a
+    common phase, which cancels in C / D and in |X|^2; relabelling the
+    antennas permutes the gains."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=1, n_samples=120, t_cal=40)
+    E = np.stack([synth.efield_channel(wl, 0)], axis=1)
+    pb = O.Problem.from_workload(wl)
+    r0 = O.run(E, pb, wl.g0)
+    pb2 = O.Problem.from_workload(wl)
+    pb2.x0 = pb.x0 - 3 * pb.dx
+    pb2.y0 = pb.y0 + 5 * pb.dy
+    r1 = O.run(E, pb2, wl.g0)
+    np.testing.assert_allclose(r1["gains"], r0["gains"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r1["image"], np.roll(r0["image"], 0, axis=(0, 1)), rtol=1e-10)
+    perm = np.random.default_rng(5).permutation(wl.array.n_ant)
+    pb3 = O.Problem.from_workload(wl)
+    pb3.ant_xy = pb.ant_xy[perm]
+    r2 = O.run(E[:, :, perm], pb3, wl.g0[:, perm])
+    np.testing.assert_allclose(r2["gains"], r0["gains"][:, :, perm], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r2["image"], r0["image"], rtol=1e-10)
+
+
+def test_split_run_equals_resume():
+    """The only state carried between intervals is g^(n) (Fig. times): a run
+    split at an interval boundary and resumed from g^(n) gives the same gains."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=1, n_samples=150, t_cal=50)
+    E = np.stack([synth.efield_channel(wl, 0)], axis=1)
+    pb = O.Problem.from_workload(wl)
+    full = O.run(E, pb, wl.g0)
+    a = O.run(E[:100], pb, wl.g0)
+    b = O.run(E[100:], pb, a["gains"][-1])
+    np.testing.assert_allclose(b["gains"][-1], full["gains"][-1], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose((a["image"] * 100 + b["image"] * 50) / 150, full["image"], rtol=1e-12)
+
+
+def test_flagged_antennas_are_ignored():
+    """Flagged antennas (Sec. 5) are held, and the rest behaves as the array
+    without them."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=1, n_samples=100, t_cal=50)
+    E = np.stack([synth.efield_channel(wl, 0)], axis=1)
+    flags = np.zeros(wl.array.n_ant, np.uint8)
+    flags[[2, 9, 30]] = 1
+    pb = O.Problem.from_workload(wl)
+    pb.flags = flags
+    r = O.run(E, pb, wl.g0)
+    np.testing.assert_array_equal(r["gains"][-1][:, flags == 1], wl.g0[:, flags == 1])
+    keep = flags == 0
+    pb2 = O.Problem.from_workload(wl)
+    pb2.ant_xy = pb.ant_xy[keep]
+    r2 = O.run(E[:, :, keep], pb2, wl.g0[:, keep])
+    np.testing.assert_allclose(r["gains"][-1][:, keep], r2["gains"][-1], rtol=1e-11)
+    np.testing.assert_allclose(r["image"], r2["image"], rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# gradient of the fixed-gain image (differentiable form)
+# ---------------------------------------------------------------------------
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(11)
+    Na, N, T = 10, 16, 6
+    xy = rng.uniform(2, 14, size=(Na, 2))
+    c = O.grid_cells(xy, 1.0, 1.0, 0.0, 0.0, N, N, 2)
+    E = crandn(T, Na, rng=rng) * 3
+    g = crandn(Na, rng=rng) * 0.3 + 1.0
+    M = rng.uniform(0, 1, size=(N, N))
+
+    def loss(gg):
+        I = O.image_fixed_gains(E, gg, c, N, N, float(Na))
+        return np.sum((I - M) ** 2)
+
+    I = O.image_fixed_gains(E, g, c, N, N, float(Na))
+    grad = O.image_gain_gradient(E, g, c, N, N, float(Na), 2 * (I - M))
+    h = 1e-6
+    for a in range(Na):
+        d = np.zeros(Na, complex)
+        d[a] = h
+        dre = (loss(g + d) - loss(g - d)) / (2 * h)
+        dim = (loss(g + 1j * d) - loss(g - 1j * d)) / (2 * h)
+        assert abs(grad[a] - (dre + 1j * dim)) <= 1e-6 * max(1.0, abs(grad[a])), a

@@ -1,0 +1,243 @@
+/*
+ * epic.h -- C ABI of the MI355X (gfx950) EPIC / EPICal library.
+ *
+ * The library runs the direct-imaging correlator loop with in-loop feedback
+ * calibration of Beardsley et al. (2016), "An Efficient Feedback Calibration
+ * Algorithm for Direct Imaging Radio Telescopes" (arXiv:1603.02126):
+ * per channel and time sample, calibrate the antenna E-fields with the
+ * current gains, grid them with the antenna kernel, take the 2D spatial
+ * transform, square and accumulate the image, correlate each antenna with the
+ * tapped calibrator pixel, and update the gains once per calibration interval
+ * with the damped solution -- without ever forming visibilities.
+ *
+ * Conventions used by every call
+ *   - Return value: EPIC_OK (0) or a negative epic_status.  Nothing aborts or
+ *     throws; epic_last_error() gives a message for the calling thread.
+ *   - "host" pointers are read during the call and may be freed afterwards.
+ *     "device" pointers are caller-owned HIP device memory (e.g. torch tensor
+ *     storage) on the plan's device; they must stay valid until the work
+ *     enqueued on `stream` has finished.  Device work is asynchronous on
+ *     `stream` (a hipStream_t; NULL = the null stream); argument checks are
+ *     synchronous and happen before anything is enqueued.
+ *   - Complex numbers are interleaved (re, im) pairs of the stated real type.
+ *   - Array layouts are C order (last index fastest); sizes are elements.
+ *   - E-field streams are [T][F][Na] packed samples in the array's format.
+ *   - Images are [F][ny][nx] in natural (unshifted) transform order: pixel
+ *     (ky, kx) with signed index kappa = k (k < N/2) or k - N (k >= N/2) lies
+ *     at direction cosine l = kappa c / (f N d) (Sec. 2.1).
+ *   - Gains g are [F][Na] complex128.  E'_a = E_a / g_a (Sec. 2.1).
+ *   - A plan is used by one host thread at a time; plans are independent.
+ */
+#ifndef EPIC_H
+#define EPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct epic_plan_s* epic_plan_t;
+typedef void* epic_stream_t; /* hipStream_t */
+
+typedef enum {
+  EPIC_OK = 0,
+  EPIC_ERR_ARG = -1,         /* bad pointer, size, shape, format or parameter */
+  EPIC_ERR_ALLOC = -2,       /* device or host allocation failed */
+  EPIC_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  EPIC_ERR_UNSUPPORTED = -4, /* valid but not implemented (e.g. grid size) */
+  EPIC_ERR_STATE = -5        /* call out of order (e.g. no model set) */
+} epic_status;
+
+/* Packed antenna E-field sample formats (the F-engine output, Sec. 2.1). */
+typedef enum {
+  EPIC_CF32 = 0, /* 8 bytes: float32 re, float32 im */
+  EPIC_CI8 = 1,  /* 2 bytes: int8 re, int8 im */
+  EPIC_CI4 = 2   /* 1 byte: re in bits 7..4, im in bits 3..0, two's complement */
+} epic_efmt;
+
+/* Per-antenna status bits (OR-ed over all updates of a run). */
+#define EPIC_ANT_FLAGGED 1u    /* flagged on input: not gridded/correlated/updated */
+#define EPIC_ANT_D_ZERO 2u     /* |D_a| <= 1e-12 max|D|: gain held */
+#define EPIC_ANT_NONFINITE 4u  /* update not finite: gain held */
+
+/* One antenna array and its aperture grid (Sec. 2.1, eq. gridding).
+ * Positions and grid are in metres.  Grid cell (jx, jy) sits at
+ * (x0 + jx dx, y0 + jy dy); cell indices wrap modulo the grid size.
+ * kernel 1 = nearest cell, jx = floor((x - x0)/dx + 0.5);
+ * kernel 2 = 2x2 bilinear (area overlap of a one-cell tophat):
+ *   i0 = floor(p), phi = p - i0, weights (1-phi, phi) per axis.
+ * nx == ny, a power of two in {16, 32, 64, 128}. */
+typedef struct {
+  int32_t n_ant;           /* Na >= 1 */
+  int32_t n_chan;          /* F >= 1 */
+  int32_t nx, ny;          /* grid size */
+  int32_t kernel;          /* 1 or 2 */
+  int32_t efmt;            /* epic_efmt */
+  double dx, dy, x0, y0;   /* cell size and origin, metres */
+  const double* ant_xy;    /* host [Na][2] antenna (x, y), metres */
+  const double* freq_hz;   /* host [F] channel frequencies, Hz (> 0) */
+  const uint8_t* ant_flag; /* host [Na], nonzero = flagged; or NULL */
+} epic_array_desc;
+
+/* Calibration model (Sec. 2.2): point-source sky for the model visibilities
+ * V^M_ab = sum_s S_s exp(-2 pi i f (r_a - r_b) . s_s / c), the calibrator
+ * direction whose nearest pixel k0 is tapped (eq. Kna_def), the damping
+ * factor (eq. damping, 0 <= gamma < 1) and the calibration interval length in
+ * samples (Fig. times). */
+typedef struct {
+  const double* src_lmS; /* host [n_src][3]: l, m, flux (data units) */
+  int32_t n_src;         /* >= 1 */
+  double cal_l, cal_m;   /* calibrator direction cosines */
+  double gamma;          /* damping, [0, 1) */
+  int32_t t_cal;         /* samples per calibration interval, >= 1 */
+} epic_model_desc;
+
+/* ---------------------------------------------------------------------- */
+/* Library information and host-only helpers (no device needed)           */
+/* ---------------------------------------------------------------------- */
+
+/* ABI version, currently 1. */
+int32_t epic_abi_version(void);
+
+/* Message describing the last error on this thread ("" if none).  Valid until
+ * the next call on this thread. */
+const char* epic_last_error(void);
+
+/* Grid cells and kernel weights of each antenna (eq. gridding), exactly as the
+ * device tables use them.  ixy: host [Na][K][2] int32 (jx, jy) after the
+ * modulo wrap; w: host [Na][K] float64; K = 1 (kernel 1) or 4 (kernel 2),
+ * cells in the order (i0,j0), (i0+1,j0), (i0,j0+1), (i0+1,j0+1).  Flagged
+ * antennas are reported like the others. */
+int epic_host_grid_cells(const epic_array_desc* desc, int32_t* ixy, double* w);
+
+/* Calibrator pixel and model-side quantities per channel, computed on the
+ * host in float64 exactly as the plan uses them.
+ *   k0: host [F][2] int32 (kx, ky), the pixel nearest (cal_l, cal_m):
+ *       kappa = floor(l f N d / c + 0.5) mod N.
+ *   A:  host [F][Na] complex128, A_a(k0) = sum_j w_aj exp(+2 pi i j . k0 / N),
+ *       the gridded antenna's response at the tapped pixel.  It stands for
+ *       the factor W_b(s0) exp(+2 pi i f s0 . r_b / c) of eq. (Cna).
+ *   D:  host [F][Na] complex128, D_a = sum_{b != a, b unflagged}
+ *       conj(A_b) V^M_ab, the denominator of eq. (cal_solution), evaluated in
+ *       O(Na * n_src) per channel by factoring V^M over sources.
+ * Any of k0, A, D may be NULL. */
+int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* model,
+                         int32_t* k0, double* A, double* D);
+
+/* ---------------------------------------------------------------------- */
+/* Plans                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Create a plan for n_arrays arrays on the current HIP device.  The plan
+ * copies the descriptors, builds the gridding tables and owns all device
+ * tables and scratch memory.  *out receives the plan. */
+int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_t* out);
+
+/* Release the plan and its device memory (synchronises the device first). */
+int epic_plan_destroy(epic_plan_t plan);
+
+/* Set the calibration model of one array (required before epical_update and
+ * epic_run): computes k0, A and D on the host and uploads them. */
+int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* model);
+
+/* Tuning options (key, value).  Keys:
+ *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)
+ *   EPIC_OPT_TRANSFORM   0 = auto, 1 = FFT (FP32), 2 = DFT-GEMM (split-precision MFMA)
+ *   EPIC_OPT_TIMING      1 = record HIP events around each kernel (see below) */
+#define EPIC_OPT_SPLITS 1
+#define EPIC_OPT_TRANSFORM 2
+#define EPIC_OPT_TIMING 3
+int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
+
+/* Kernel timing, when EPIC_OPT_TIMING is on.  Events are recorded on the
+ * stream each kernel is launched on.  Fills ms[k] with the total elapsed
+ * milliseconds and launches[k] with the launch count of kernel kind k since
+ * the last call, for k < n (kinds: 0 calibration solve, 1 imaging,
+ * 2 image reduction, 3 adjoint); waits for the recorded events. */
+#define EPIC_TIMER_SOLVE 0
+#define EPIC_TIMER_IMAGE 1
+#define EPIC_TIMER_REDUCE 2
+#define EPIC_TIMER_ADJOINT 3
+#define EPIC_TIMER_COUNT 4
+int epic_plan_get_timing(epic_plan_t plan, double* ms, int64_t* launches, int32_t n);
+
+/* ---------------------------------------------------------------------- */
+/* Stage-wise calls (each stage of the loop on its own, through HBM)       */
+/* ---------------------------------------------------------------------- */
+
+/* Calibrate and grid (Sec. 2.1: E'_a = E_a u_a, eq. gridding):
+ *   grid[t][f][jy][jx] = sum_a sum_k w_ak [cell_ak == (jx,jy)] E_a(t0+t, f) u[f][a]
+ * efield: device [T][F][Na] packed, samples t0 .. t0+nt-1 are read.
+ * u:      device [F][Na] complex64, the applied calibration 1/g (any values).
+ * grid:   device [nt][F][ny][nx] complex64, overwritten.
+ * Flagged antennas are not gridded. */
+int epic_grid(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, int32_t nt,
+              const float* u, float* grid, epic_stream_t stream);
+
+/* Transform, square and accumulate (Sec. 2.1 MOFF summary equation; squaring
+ * and time averaging):
+ *   X_t(k) = (1/Na) sum_j grid[t][f][j] exp(+2 pi i (jx kx/nx + jy ky/ny))
+ *   image[f][ky][kx] += sum_t |X_t(k)|^2     (not divided by nt)
+ *   tap[t][f] = X_t(k0_f)                    (if tap != NULL; needs a model)
+ * grid: device [nt][F][ny][nx] complex64; image: device [F][ny][nx] float32,
+ * accumulated; tap: device [nt][F] complex64 or NULL.  Na = unflagged count. */
+int epic_image_accumulate(epic_plan_t plan, int32_t array, const float* grid, int32_t nt,
+                          float* image, float* tap, epic_stream_t stream);
+
+/* EPICal correlation and update (eq. Kna_def, Cna, damping):
+ *   kq[f][a] += (sum_t E_a(t) conj(tap[t][f]), sum_t |E_a(t)|^2, nt)
+ * with the uncalibrated E-fields of samples t0 .. t0+nt-1.  If finalize != 0,
+ * then with Kbar = K/n, Qbar = Q/n:
+ *   C_a = Kbar_a - conj(A_a) Qbar_a / (Na conj(g_a))
+ *   g_a <- (1 - gamma) Na C_a / D_a + gamma g_a
+ * (gains held for flagged antennas, |D_a| <= 1e-12 max|D|, or a non-finite
+ * update), and kq is reset to zero.
+ * efield: device packed; tap: device [nt][F] complex64; kq: device [F][Na][4]
+ * float64 (K re, K im, Q, n), zero it before the first call of an interval;
+ * gains: device [F][Na] complex128 in/out; status: device [F][Na] uint32 OR-ed
+ * with EPIC_ANT_* bits, or NULL.  nt may be 0 (finalize only). */
+int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, int32_t nt,
+                  const float* tap, double* kq, double* gains, int32_t finalize,
+                  uint32_t* status, epic_stream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* The fused loop                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Run the calibrated EPIC loop over n_samples samples of every array
+ * (Fig. schematic): interval n (t_cal samples, the last may be short) is
+ * calibrated with g^(n); its tapped pixel and uncalibrated E-fields give
+ * g^(n+1) by eq. (damping).  The tapped pixel is evaluated as the equal
+ * beamformed sum (1/Na) sum_a A_a(k0) E_a / g_a of the gridded transform.
+ * Per array i:
+ *   efield[i]:    device [n_samples][F][Na] packed
+ *   gains[i]:     device [F][Na] complex128; in: g^(0), out: g^(n_int)
+ *   image[i]:     device [F][ny][nx] float32, out: (1/n_samples) sum_t |X_t|^2
+ *   gain_hist[i]: device [n_int+1][F][Na] complex128 (g^(0) .. g^(n_int)) or NULL
+ *   ant_status[i]:device [F][Na] uint32 (EPIC_ANT_* bits) or NULL
+ * gain_hist and ant_status may themselves be NULL. */
+int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+             float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
+             epic_stream_t stream);
+
+/* Fixed-gain imaging of one array (the loop with calibration frozen):
+ *   image[f] = (1/n_samples) sum_t |X_t|^2 with E'_a = E_a u[f][a].
+ * u: device [F][Na] complex64 (= 1/g).  image: device [F][ny][nx] float32. */
+int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples,
+               const float* u, float* image, epic_stream_t stream);
+
+/* Adjoint of epic_image with respect to the gains, for a real loss L(image):
+ * given dL_dI = dL/dimage (device [F][ny][nx] float32) and the gains g
+ * (device [F][Na] complex128; u = 1/g is applied), writes
+ *   dL_dg[f][a] = dL/dRe g + i dL/dIm g  (= 2 dL/dg*)
+ * as device [F][Na] complex128.  Per-sample transforms are recomputed, not
+ * stored. */
+int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples,
+                       const double* gains, const float* dL_dI, double* dL_dg,
+                       epic_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPIC_H */

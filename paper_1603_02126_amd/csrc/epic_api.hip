@@ -1,0 +1,648 @@
+// Host side of the EPIC library: argument checks, plan tables (gridding
+// cells, calibrator pixel response, model denominator), scratch memory,
+// dispatch and the extern "C" entry points declared in include/epic.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/epic.h"
+#include "epic_internal.h"
+
+using epic::ImageArgs;
+using zc = std::complex<double>;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(EPIC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Validated copy of one epic_array_desc.
+struct HostArray {
+  int na = 0, F = 0, nx = 0, ny = 0, kernel = 1, efmt = 0, k2 = 1;
+  double dx = 0, dy = 0, x0 = 0, y0 = 0;
+  std::vector<double> xy, freq;
+  std::vector<uint8_t> flag;
+  int na_eff = 0;
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_desc(const epic_array_desc* d, HostArray* out) {
+  if (!d) return fail(EPIC_ERR_ARG, "array descriptor is NULL");
+  if (d->n_ant < 1) return fail(EPIC_ERR_ARG, "n_ant must be >= 1 (got %d)", d->n_ant);
+  if (d->n_chan < 1) return fail(EPIC_ERR_ARG, "n_chan must be >= 1 (got %d)", d->n_chan);
+  if (!is_pow2(d->nx) || !is_pow2(d->ny) || d->nx < 2 || d->ny < 2 || d->nx > 4096 || d->ny > 4096)
+    return fail(EPIC_ERR_ARG, "nx, ny must be powers of two in [2, 4096] (got %d x %d)", d->nx, d->ny);
+  if (d->kernel != 1 && d->kernel != 2) return fail(EPIC_ERR_ARG, "kernel must be 1 or 2 (got %d)", d->kernel);
+  if (d->efmt < EPIC_CF32 || d->efmt > EPIC_CI4) return fail(EPIC_ERR_ARG, "unknown efmt %d", d->efmt);
+  if (!(d->dx > 0) || !(d->dy > 0) || !std::isfinite(d->dx) || !std::isfinite(d->dy))
+    return fail(EPIC_ERR_ARG, "dx, dy must be positive and finite");
+  if (!std::isfinite(d->x0) || !std::isfinite(d->y0)) return fail(EPIC_ERR_ARG, "x0, y0 must be finite");
+  if (!d->ant_xy) return fail(EPIC_ERR_ARG, "ant_xy is NULL");
+  if (!d->freq_hz) return fail(EPIC_ERR_ARG, "freq_hz is NULL");
+  HostArray h;
+  h.na = d->n_ant;
+  h.F = d->n_chan;
+  h.nx = d->nx;
+  h.ny = d->ny;
+  h.kernel = d->kernel;
+  h.k2 = d->kernel == 1 ? 1 : 4;
+  h.efmt = d->efmt;
+  h.dx = d->dx;
+  h.dy = d->dy;
+  h.x0 = d->x0;
+  h.y0 = d->y0;
+  h.xy.assign(d->ant_xy, d->ant_xy + 2 * size_t(h.na));
+  h.freq.assign(d->freq_hz, d->freq_hz + h.F);
+  for (double v : h.xy)
+    if (!std::isfinite(v)) return fail(EPIC_ERR_ARG, "antenna positions must be finite");
+  for (double v : h.freq)
+    if (!(v > 0) || !std::isfinite(v)) return fail(EPIC_ERR_ARG, "frequencies must be positive and finite");
+  h.flag.assign(h.na, 0);
+  if (d->ant_flag)
+    for (int a = 0; a < h.na; ++a) h.flag[a] = d->ant_flag[a] ? 1 : 0;
+  h.na_eff = 0;
+  for (int a = 0; a < h.na; ++a) h.na_eff += h.flag[a] == 0;
+  if (out) *out = std::move(h);
+  return EPIC_OK;
+}
+
+// Gridding cells and weights (eq. gridding): nearest cell or 2x2 bilinear
+// (area overlap of a one-cell tophat); indices wrap modulo the grid size.
+void grid_cells(const HostArray& h, std::vector<int32_t>& ix, std::vector<int32_t>& iy, std::vector<double>& w) {
+  ix.assign(size_t(h.na) * h.k2, 0);
+  iy.assign(size_t(h.na) * h.k2, 0);
+  w.assign(size_t(h.na) * h.k2, 0.0);
+  auto wrap = [](long long v, int n) { long long r = v % n; return int32_t(r < 0 ? r + n : r); };
+  for (int a = 0; a < h.na; ++a) {
+    const double px = (h.xy[2 * a] - h.x0) / h.dx;
+    const double py = (h.xy[2 * a + 1] - h.y0) / h.dy;
+    if (h.kernel == 1) {
+      ix[a] = wrap((long long)std::floor(px + 0.5), h.nx);
+      iy[a] = wrap((long long)std::floor(py + 0.5), h.ny);
+      w[a] = 1.0;
+    } else {
+      const double fx = std::floor(px), fy = std::floor(py);
+      const double ax = px - fx, ay = py - fy;
+      const long long i0 = (long long)fx, j0 = (long long)fy;
+      const long long cx[4] = {i0, i0 + 1, i0, i0 + 1}, cy[4] = {j0, j0, j0 + 1, j0 + 1};
+      const double cw[4] = {(1 - ax) * (1 - ay), ax * (1 - ay), (1 - ax) * ay, ax * ay};
+      for (int k = 0; k < 4; ++k) {
+        ix[4 * a + k] = wrap(cx[k], h.nx);
+        iy[4 * a + k] = wrap(cy[k], h.ny);
+        w[4 * a + k] = cw[k];
+      }
+    }
+  }
+}
+
+struct ModelTables {
+  std::vector<int32_t> k0;   // [F][2]
+  std::vector<zc> A, D;      // [F][Na]
+  std::vector<uint8_t> hold; // [F][Na]
+};
+
+int check_model(const epic_model_desc* m) {
+  if (!m) return fail(EPIC_ERR_ARG, "model descriptor is NULL");
+  if (!m->src_lmS || m->n_src < 1) return fail(EPIC_ERR_ARG, "model needs at least one source");
+  if (!(m->gamma >= 0.0 && m->gamma < 1.0)) return fail(EPIC_ERR_ARG, "gamma must be in [0, 1) (got %g)", m->gamma);
+  if (m->t_cal < 1) return fail(EPIC_ERR_ARG, "t_cal must be >= 1 (got %d)", m->t_cal);
+  if (!std::isfinite(m->cal_l) || !std::isfinite(m->cal_m)) return fail(EPIC_ERR_ARG, "calibrator direction not finite");
+  for (int s = 0; s < 3 * m->n_src; ++s)
+    if (!std::isfinite(m->src_lmS[s])) return fail(EPIC_ERR_ARG, "model sources must be finite");
+  return EPIC_OK;
+}
+
+// k0, A_a(k0) and the model denominator D_a per channel.
+//   A_a = sum_k w_ak exp(+2 pi i (jx kx / nx + jy ky / ny))
+//   D_a = sum_{b != a, unflagged} conj(A_b) V^M_ab,
+//   V^M_ab = sum_s S_s e_a(s) conj(e_b(s)),  e_a(s) = exp(-2 pi i f r_a . s / c)
+// factored as D_a = sum_s S_s e_a(s) B(s) - [a unflagged] conj(A_a) sum_s S_s
+// with B(s) = sum_{b unflagged} conj(A_b) conj(e_b(s)).
+void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) {
+  std::vector<int32_t> ix, iy;
+  std::vector<double> w;
+  grid_cells(h, ix, iy, w);
+  t.k0.assign(2 * size_t(h.F), 0);
+  t.A.assign(size_t(h.F) * h.na, zc(0, 0));
+  t.D.assign(size_t(h.F) * h.na, zc(0, 0));
+  t.hold.assign(size_t(h.F) * h.na, 0);
+  const int ns = m->n_src;
+  double Stot = 0;
+  for (int s = 0; s < ns; ++s) Stot += m->src_lmS[3 * s + 2];
+  std::vector<zc> e(size_t(h.na) * ns);
+  for (int f = 0; f < h.F; ++f) {
+    const double fr = h.freq[f];
+    const long long kxs = (long long)std::floor(m->cal_l * fr * h.nx * h.dx / kC + 0.5);
+    const long long kys = (long long)std::floor(m->cal_m * fr * h.ny * h.dy / kC + 0.5);
+    const long long kx = ((kxs % h.nx) + h.nx) % h.nx, ky = ((kys % h.ny) + h.ny) % h.ny;
+    t.k0[2 * f] = int32_t(kx);
+    t.k0[2 * f + 1] = int32_t(ky);
+    zc* A = &t.A[size_t(f) * h.na];
+    for (int a = 0; a < h.na; ++a) {
+      zc s(0, 0);
+      for (int k = 0; k < h.k2; ++k) {
+        const size_t q = size_t(a) * h.k2 + k;
+        const double ph = kTwoPi * (double((ix[q] * kx) % h.nx) / h.nx + double((iy[q] * ky) % h.ny) / h.ny);
+        s += w[q] * zc(std::cos(ph), std::sin(ph));
+      }
+      A[a] = s;
+    }
+    for (int a = 0; a < h.na; ++a)
+      for (int s = 0; s < ns; ++s) {
+        const double l = m->src_lmS[3 * s], mm = m->src_lmS[3 * s + 1];
+        const double ph = -kTwoPi * fr * (h.xy[2 * a] * l + h.xy[2 * a + 1] * mm) / kC;
+        e[size_t(a) * ns + s] = zc(std::cos(ph), std::sin(ph));
+      }
+    std::vector<zc> B(ns, zc(0, 0));
+    for (int b = 0; b < h.na; ++b) {
+      if (h.flag[b]) continue;
+      for (int s = 0; s < ns; ++s) B[s] += std::conj(A[b]) * std::conj(e[size_t(b) * ns + s]);
+    }
+    zc* D = &t.D[size_t(f) * h.na];
+    double dmax = 0;
+    for (int a = 0; a < h.na; ++a) {
+      zc acc(0, 0);
+      for (int s = 0; s < ns; ++s) acc += m->src_lmS[3 * s + 2] * e[size_t(a) * ns + s] * B[s];
+      if (!h.flag[a]) acc -= std::conj(A[a]) * Stot;
+      D[a] = acc;
+      dmax = std::max(dmax, std::abs(acc));
+    }
+    for (int a = 0; a < h.na; ++a) {
+      uint8_t hb = 0;
+      if (h.flag[a]) hb |= epic::kHoldFlagged;
+      if (!(std::abs(D[a]) > 1e-12 * dmax)) hb |= epic::kHoldDZero;
+      t.hold[size_t(f) * h.na + a] = hb;
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct ArrayPlan {
+  HostArray h;
+  uint32_t* d_cell_ixy = nullptr;
+  float* d_cell_w = nullptr;
+  bool has_model = false;
+  double gamma = 0;
+  int t_cal = 1;
+  int32_t* d_k0 = nullptr;
+  double2* d_A = nullptr;
+  double2* d_D = nullptr;
+  uint8_t* d_hold = nullptr;
+};
+
+struct TimerRec {
+  int kind;
+  hipEvent_t a, b;
+};
+
+struct epic_plan_s {
+  int device = 0;
+  std::vector<ArrayPlan> arrays;
+  // scratch
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // options
+  int splits = 0;
+  int transform = 0;
+  bool timing = false;
+  std::vector<TimerRec> timers;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+void free_array(ArrayPlan& p) {
+  hipFree(p.d_cell_ixy);
+  hipFree(p.d_cell_w);
+  hipFree(p.d_k0);
+  hipFree(p.d_A);
+  hipFree(p.d_D);
+  hipFree(p.d_hold);
+  p = ArrayPlan{};
+}
+
+template <typename T>
+int upload(T** dst, const T* src, size_t n) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return fail(EPIC_ERR_ALLOC, "hipMalloc(%zu bytes): %s", n * sizeof(T), hipGetErrorString(e));
+  if (n) {
+    e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  return EPIC_OK;
+}
+
+int scratch(epic_plan_t p, size_t bytes, void** out) {
+  if (bytes > p->scratch_bytes) {
+    if (p->d_scratch) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      hipFree(p->d_scratch);
+      p->d_scratch = nullptr;
+      p->scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p->d_scratch, bytes);
+    if (e != hipSuccess) return fail(EPIC_ERR_ALLOC, "scratch hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    p->scratch_bytes = bytes;
+  }
+  *out = p->d_scratch;
+  return EPIC_OK;
+}
+
+int check_plan(epic_plan_t p, int array) {
+  if (!p) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (array < 0 || array >= int(p->arrays.size()))
+    return fail(EPIC_ERR_ARG, "array index %d out of range [0, %zu)", array, p->arrays.size());
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != p->device) return fail(EPIC_ERR_ARG, "current device %d is not the plan's device %d", dev, p->device);
+  return EPIC_OK;
+}
+
+int check_grid_supported(const ArrayPlan& ap) {
+  const HostArray& h = ap.h;
+  if (h.nx != h.ny) return fail(EPIC_ERR_UNSUPPORTED, "only square grids are implemented (got %d x %d)", h.nx, h.ny);
+  if (!epic::image_supported(h.nx, h.k2, h.na))
+    return fail(EPIC_ERR_UNSUPPORTED, "grid %d with %d antennas is not supported (N in {16,32,64}, Na <= 8N)",
+                h.nx, h.na);
+  return EPIC_OK;
+}
+
+struct Timed {
+  epic_plan_t p;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(epic_plan_t p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
+    if (!p->timing) return;
+    a = take();
+    b = take();
+    if (a) hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    if (!p->event_pool.empty()) {
+      hipEvent_t e = p->event_pool.back();
+      p->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~Timed() {
+    if (!p->timing || !a || !b) return;
+    hipEventRecord(b, s);
+    p->timers.push_back({kind, a, b});
+  }
+};
+
+int pick_splits(epic_plan_t p, int F, int64_t T, int slots) {
+  if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
+  // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames per slot
+  int64_t s = (2048 + F - 1) / F;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, T / (8 * int64_t(slots))));
+  return int(std::max<int64_t>(1, s));
+}
+
+int slots_for(int N) { return 4 * (64 / N); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t epic_abi_version(void) { return 1; }
+
+const char* epic_last_error(void) { return g_err.c_str(); }
+
+int epic_host_grid_cells(const epic_array_desc* desc, int32_t* ixy, double* w) {
+  HostArray h;
+  int rc = check_desc(desc, &h);
+  if (rc) return rc;
+  if (!ixy || !w) return fail(EPIC_ERR_ARG, "output pointers must not be NULL");
+  std::vector<int32_t> ix, iy;
+  std::vector<double> ww;
+  grid_cells(h, ix, iy, ww);
+  for (size_t q = 0; q < ix.size(); ++q) {
+    ixy[2 * q] = ix[q];
+    ixy[2 * q + 1] = iy[q];
+    w[q] = ww[q];
+  }
+  return EPIC_OK;
+}
+
+int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* model, int32_t* k0, double* A,
+                         double* D) {
+  HostArray h;
+  int rc = check_desc(desc, &h);
+  if (rc) return rc;
+  rc = check_model(model);
+  if (rc) return rc;
+  ModelTables t;
+  model_tables(h, model, t);
+  if (k0) std::memcpy(k0, t.k0.data(), t.k0.size() * sizeof(int32_t));
+  if (A) std::memcpy(A, t.A.data(), t.A.size() * sizeof(zc));
+  if (D) std::memcpy(D, t.D.data(), t.D.size() * sizeof(zc));
+  return EPIC_OK;
+}
+
+int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_t* out) {
+  if (!out) return fail(EPIC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!arrays || n_arrays < 1) return fail(EPIC_ERR_ARG, "need at least one array descriptor");
+  std::vector<HostArray> hs(n_arrays);
+  for (int i = 0; i < n_arrays; ++i) {
+    int rc = check_desc(&arrays[i], &hs[i]);
+    if (rc) return rc;
+  }
+  epic_plan_t p = new (std::nothrow) epic_plan_s;
+  if (!p) return fail(EPIC_ERR_ALLOC, "host allocation failed");
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  p->arrays.resize(n_arrays);
+  for (int i = 0; i < n_arrays; ++i) {
+    ArrayPlan& ap = p->arrays[i];
+    ap.h = std::move(hs[i]);
+    std::vector<int32_t> ix, iy;
+    std::vector<double> w;
+    grid_cells(ap.h, ix, iy, w);
+    std::vector<uint32_t> packed(ix.size());
+    std::vector<float> wf(ix.size());
+    for (size_t q = 0; q < ix.size(); ++q) {
+      packed[q] = (uint32_t(iy[q]) << 16) | uint32_t(ix[q]);
+      wf[q] = ap.h.flag[q / ap.h.k2] ? 0.f : float(w[q]);
+    }
+    int rc = upload(&ap.d_cell_ixy, packed.data(), packed.size());
+    if (!rc) rc = upload(&ap.d_cell_w, wf.data(), wf.size());
+    if (rc) {
+      epic_plan_destroy(p);
+      return rc;
+    }
+  }
+  *out = p;
+  return EPIC_OK;
+}
+
+int epic_plan_destroy(epic_plan_t plan) {
+  if (!plan) return EPIC_OK;
+  hipDeviceSynchronize();
+  for (auto& ap : plan->arrays) free_array(ap);
+  hipFree(plan->d_scratch);
+  for (auto& t : plan->timers) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : plan->event_pool) hipEventDestroy(e);
+  delete plan;
+  return EPIC_OK;
+}
+
+int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* model) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  rc = check_model(model);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if (ap.h.na_eff < 2) return fail(EPIC_ERR_ARG, "calibration needs at least two unflagged antennas");
+  ModelTables t;
+  model_tables(ap.h, model, t);
+  hipFree(ap.d_k0);
+  hipFree(ap.d_A);
+  hipFree(ap.d_D);
+  hipFree(ap.d_hold);
+  ap.d_k0 = nullptr;
+  ap.d_A = ap.d_D = nullptr;
+  ap.d_hold = nullptr;
+  ap.has_model = false;
+  rc = upload(&ap.d_k0, t.k0.data(), t.k0.size());
+  if (!rc) rc = upload(&ap.d_A, reinterpret_cast<const double2*>(t.A.data()), t.A.size());
+  if (!rc) rc = upload(&ap.d_D, reinterpret_cast<const double2*>(t.D.data()), t.D.size());
+  if (!rc) rc = upload(&ap.d_hold, t.hold.data(), t.hold.size());
+  if (rc) return rc;
+  ap.gamma = model->gamma;
+  ap.t_cal = model->t_cal;
+  ap.has_model = true;
+  return EPIC_OK;
+}
+
+int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  switch (key) {
+    case EPIC_OPT_SPLITS:
+      if (value < 0 || value > (1 << 20)) return fail(EPIC_ERR_ARG, "splits out of range");
+      plan->splits = int(value);
+      return EPIC_OK;
+    case EPIC_OPT_TRANSFORM:
+      if (value < 0 || value > 2) return fail(EPIC_ERR_ARG, "transform must be 0, 1 or 2");
+      plan->transform = int(value);
+      return EPIC_OK;
+    case EPIC_OPT_TIMING:
+      plan->timing = value != 0;
+      return EPIC_OK;
+    default:
+      return fail(EPIC_ERR_ARG, "unknown option key %d", key);
+  }
+}
+
+int epic_plan_get_timing(epic_plan_t plan, double* ms, int64_t* launches, int32_t n) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(EPIC_ERR_ARG, "bad output arrays");
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0;
+    launches[k] = 0;
+  }
+  int rc = EPIC_OK;
+  for (auto& t : plan->timers) {
+    hipError_t e = hipEventSynchronize(t.b);
+    float el = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, t.a, t.b);
+    if (e != hipSuccess && rc == EPIC_OK) rc = hip_fail(e, "hipEventElapsedTime");
+    if (t.kind < n) {
+      ms[t.kind] += el;
+      launches[t.kind] += 1;
+    }
+    plan->event_pool.push_back(t.a);
+    plan->event_pool.push_back(t.b);
+  }
+  plan->timers.clear();
+  return rc;
+}
+
+int epic_grid(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, int32_t nt, const float* u,
+              float* grid, epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if ((rc = check_grid_supported(ap))) return rc;
+  if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
+  if (nt > 0 && (!efield || !u || !grid)) return fail(EPIC_ERR_ARG, "efield, u and grid must not be NULL");
+  epic::GridArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
+                   reinterpret_cast<const float2*>(u), ap.d_cell_ixy, ap.d_cell_w, reinterpret_cast<float2*>(grid)};
+  hipError_t e = epic::launch_grid(ap.h.nx, ap.h.k2, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "epic_grid launch");
+}
+
+int epic_image_accumulate(epic_plan_t plan, int32_t array, const float* grid, int32_t nt, float* image, float* tap,
+                          epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if ((rc = check_grid_supported(ap))) return rc;
+  if (nt < 0) return fail(EPIC_ERR_ARG, "nt must be >= 0");
+  if (nt > 0 && (!grid || !image)) return fail(EPIC_ERR_ARG, "grid and image must not be NULL");
+  if (tap && !ap.has_model) return fail(EPIC_ERR_STATE, "tap requested but no model (calibrator pixel) set");
+  if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
+  epic::ImageAccArgs a{reinterpret_cast<const float2*>(grid), nt, ap.h.F, float(1.0 / ap.h.na_eff), image,
+                       reinterpret_cast<float2*>(tap), tap ? ap.d_k0 : nullptr};
+  hipError_t e = epic::launch_image_acc(ap.h.nx, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "epic_image_accumulate launch");
+}
+
+int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, int32_t nt, const float* tap,
+                  double* kq, double* gains, int32_t finalize, uint32_t* status, epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", array);
+  if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
+  if (!kq || !gains) return fail(EPIC_ERR_ARG, "kq and gains must not be NULL");
+  if (nt > 0 && (!efield || !tap)) return fail(EPIC_ERR_ARG, "efield and tap must not be NULL");
+  epic::UpdateArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
+                     reinterpret_cast<const float2*>(tap), kq, reinterpret_cast<double2*>(gains), ap.d_A, ap.d_D,
+                     ap.d_hold, double(ap.h.na_eff), ap.gamma, finalize ? 1 : 0, status};
+  hipError_t e = epic::launch_update(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "epical_update launch");
+}
+
+static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64_t n_samples, const float2* u,
+                      int64_t t_cal, float* image, hipStream_t s, float* partial, int splits) {
+  const HostArray& h = ap.h;
+  const int N = h.nx;
+  ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
+               ap.d_cell_ixy, ap.d_cell_w, splits, partial};
+  {
+    Timed tm(plan, EPIC_TIMER_IMAGE, s);
+    hipError_t e = epic::launch_image(N, h.k2, ia, s);
+    if (e != hipSuccess) return hip_fail(e, "imaging launch");
+  }
+  {
+    Timed tm(plan, EPIC_TIMER_REDUCE, s);
+    const double scale = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
+    hipError_t e = epic::launch_reduce(partial, splits, int64_t(h.F) * N * N, scale, image, s);
+    if (e != hipSuccess) return hip_fail(e, "image reduction launch");
+  }
+  return EPIC_OK;
+}
+
+int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+             float* const* image, double* const* gain_hist, uint32_t* const* ant_status, epic_stream_t stream) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image arrays must not be NULL");
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  const int na_arr = int(plan->arrays.size());
+  size_t need = 0;
+  for (int i = 0; i < na_arr; ++i) {
+    int rc = check_plan(plan, i);
+    if (rc) return rc;
+    ArrayPlan& ap = plan->arrays[i];
+    if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", i);
+    if ((rc = check_grid_supported(ap))) return rc;
+    if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
+    const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
+    const int splits = pick_splits(plan, ap.h.F, n_samples, slots_for(ap.h.nx));
+    const size_t uh = size_t(n_int) * ap.h.F * ap.h.na * sizeof(float2);
+    const size_t pt = size_t(splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float);
+    need = std::max(need, ((uh + 255) / 256) * 256 + pt);
+  }
+  void* scr = nullptr;
+  int rc = scratch(plan, need, &scr);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < na_arr; ++i) {
+    ArrayPlan& ap = plan->arrays[i];
+    const HostArray& h = ap.h;
+    const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
+    if (n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
+    const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+    float2* uhist = static_cast<float2*>(scr);
+    const size_t uh = size_t(n_int) * h.F * h.na * sizeof(float2);
+    float* partial = reinterpret_cast<float*>(static_cast<char*>(scr) + ((uh + 255) / 256) * 256);
+    epic::SolveArgs sa{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt, ap.t_cal,
+                       int(n_int), ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma,
+                       reinterpret_cast<double2*>(gains[i]), uhist,
+                       gain_hist ? reinterpret_cast<double2*>(gain_hist[i]) : nullptr,
+                       ant_status ? ant_status[i] : nullptr};
+    {
+      Timed tm(plan, EPIC_TIMER_SOLVE, s);
+      hipError_t e = epic::launch_solve(sa, s);
+      if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
+    }
+    rc = image_pass(plan, ap, efield[i], n_samples, uhist, ap.t_cal, image[i], s, partial, splits);
+    if (rc) return rc;
+  }
+  return EPIC_OK;
+}
+
+int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const float* u, float* image,
+               epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if ((rc = check_grid_supported(ap))) return rc;
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  if (!efield || !u || !image) return fail(EPIC_ERR_ARG, "efield, u and image must not be NULL");
+  if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
+  const int splits = pick_splits(plan, ap.h.F, n_samples, slots_for(ap.h.nx));
+  void* scr = nullptr;
+  rc = scratch(plan, size_t(splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float), &scr);
+  if (rc) return rc;
+  return image_pass(plan, ap, efield, n_samples, reinterpret_cast<const float2*>(u),
+                    std::numeric_limits<int64_t>::max(), image, static_cast<hipStream_t>(stream),
+                    static_cast<float*>(scr), splits);
+}
+
+int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const double* gains,
+                       const float* dL_dI, double* dL_dg, epic_stream_t stream) {
+  (void)efield;
+  (void)n_samples;
+  (void)gains;
+  (void)dL_dI;
+  (void)dL_dg;
+  (void)stream;
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  return fail(EPIC_ERR_UNSUPPORTED, "epic_image_adjoint is not implemented yet");
+}
+
+}  // extern "C"

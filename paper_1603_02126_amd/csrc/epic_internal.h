@@ -1,0 +1,112 @@
+// Internal interface between the host side of the library (plans, argument
+// checks, dispatch) and the HIP kernels.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epic {
+
+// Packed sample formats (same values as epic_efmt).
+enum : int { kCF32 = 0, kCI8 = 1, kCI4 = 2 };
+
+__host__ __device__ inline int efmt_bytes(int fmt) { return fmt == kCF32 ? 8 : fmt == kCI8 ? 2 : 1; }
+
+// Hold bits per (channel, antenna), precomputed on the host.
+enum : uint8_t { kHoldFlagged = 1, kHoldDZero = 2 };
+
+// Fused imaging: calibrate + grid + 2D transform + |X|^2 accumulation over a
+// range of samples, one partial image per (split, channel).
+struct ImageArgs {
+  const uint8_t* efield;    // [T][F][Na] packed
+  int64_t n_t;              // samples processed (t = 0 .. n_t-1)
+  int F, Na, fmt;
+  const float2* u;          // [n_int][F][Na]: u of interval t / t_cal
+  int64_t t_cal;
+  const uint32_t* cell_ixy; // [Na][K2] (iy << 16) | ix
+  const float* cell_w;      // [Na][K2] (0 for flagged antennas)
+  int splits;               // workgroups per channel
+  float* partial;           // [splits][F][N*N]
+};
+
+// Stage-wise gridding to HBM.
+struct GridArgs {
+  const uint8_t* efield;
+  int64_t t0;
+  int nt, F, Na, fmt;
+  const float2* u;          // [F][Na]
+  const uint32_t* cell_ixy;
+  const float* cell_w;
+  float2* grid;             // [nt][F][N][N]
+};
+
+// Stage-wise transform + accumulate from HBM grids.
+struct ImageAccArgs {
+  const float2* grid;       // [nt][F][N][N]
+  int nt, F;
+  float inv_na;             // 1 / Na
+  float* image;             // [F][N][N] +=
+  float2* tap;              // [nt][F] or null
+  const int* k0;            // [F][2] (kx, ky)
+};
+
+// EPICal solve over all intervals (fast path).
+struct SolveArgs {
+  const uint8_t* efield;
+  int64_t n_t;
+  int F, Na, fmt;
+  int64_t t_cal;
+  int n_int;
+  const double2* A;         // [F][Na]
+  const double2* D;         // [F][Na]
+  const uint8_t* hold;      // [F][Na] kHold* bits
+  double na_eff, gamma;
+  double2* gains;           // [F][Na] in/out
+  float2* u_hist;           // [n_int][F][Na]
+  double2* g_hist;          // [n_int+1][F][Na] or null
+  uint32_t* status;         // [F][Na] or null
+};
+
+// Stage-wise EPICal accumulate / finalize.
+struct UpdateArgs {
+  const uint8_t* efield;
+  int64_t t0;
+  int nt, F, Na, fmt;
+  const float2* tap;        // [nt][F]
+  double* kq;               // [F][Na][4]
+  double2* gains;
+  const double2* A;
+  const double2* D;
+  const uint8_t* hold;
+  double na_eff, gamma;
+  int finalize;
+  uint32_t* status;
+};
+
+// Adjoint of fixed-gain imaging.
+struct AdjointArgs {
+  const uint8_t* efield;
+  int64_t n_t;
+  int F, Na, fmt;
+  const float2* u;          // [F][Na]
+  const float* R;           // [F][N][N] dL/dI
+  const uint32_t* cell_ixy;
+  const float* cell_w;
+  int splits;
+  float2* partial;          // [splits][F][Na] sum_t conj(E) * degrid(...)
+};
+
+// Launchers: return hipSuccess or the launch error.  N = grid size.
+bool image_supported(int N, int k2, int na);
+hipError_t launch_image(int N, int k2, const ImageArgs& a, hipStream_t s);
+hipError_t launch_grid(int N, int k2, const GridArgs& a, hipStream_t s);
+hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
+hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
+                         float* image, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_adjoint(int N, int k2, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_adjoint_reduce(const float2* partial, int splits, int F, int Na,
+                                 const double2* gains, double scale, double2* dL_dg,
+                                 hipStream_t s);
+
+}  // namespace epic

@@ -222,17 +222,19 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
              epic_stream_t stream);
 
 /* Fixed-gain imaging of one array (the loop with calibration frozen):
- *   image[f] = (1/n_samples) sum_t |X_t|^2 with E'_a = E_a u[f][a].
- * u: device [F][Na] complex64 (= 1/g).  image: device [F][ny][nx] float32. */
+ *   image[f] = (1/n_samples) sum_t |X_t|^2 with E'_a = E_a / g[f][a].
+ * gains: device [F][Na] complex128.  image: device [F][ny][nx] float32. */
 int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples,
-               const float* u, float* image, epic_stream_t stream);
+               const double* gains, float* image, epic_stream_t stream);
 
 /* Adjoint of epic_image with respect to the gains, for a real loss L(image):
  * given dL_dI = dL/dimage (device [F][ny][nx] float32) and the gains g
- * (device [F][Na] complex128; u = 1/g is applied), writes
+ * (device [F][Na] complex128), writes
  *   dL_dg[f][a] = dL/dRe g + i dL/dIm g  (= 2 dL/dg*)
- * as device [F][Na] complex128.  Per-sample transforms are recomputed, not
- * stored. */
+ * as device [F][Na] complex128 (zero for flagged antennas).  Per-sample
+ * transforms are recomputed, not stored:
+ *   dL/dg*_a = conj(-1/g_a^2) (1/(T Na^2)) sum_t conj(E_a(t))
+ *              sum_k w_ak [DFT-(R . DFT+(G_t))](cell_ak),   R = dL_dI. */
 int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples,
                        const double* gains, const float* dL_dI, double* dL_dg,
                        epic_stream_t stream);

@@ -1,0 +1,268 @@
+// Device building blocks shared by the imaging, adjoint and calibration
+// kernels (gfx950, wave64).
+#pragma once
+#include "epic_internal.h"
+#include "fft_reg.h"
+
+namespace epic {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+// A raw packed sample held in registers until it is used (so that a prefetch
+// does not force the wait for the load at the point of issue).
+struct Raw {
+  uint32_t x, y;
+};
+
+__device__ __forceinline__ Raw load_raw(const uint8_t* row, int a, int fmt) {
+  Raw r;
+  if (fmt == kCI4) {
+    r.x = row[a];
+    r.y = 0;
+  } else if (fmt == kCI8) {
+    r.x = reinterpret_cast<const uint16_t*>(row)[a];
+    r.y = 0;
+  } else {
+    const uint2 v = reinterpret_cast<const uint2*>(row)[a];
+    r.x = v.x;
+    r.y = v.y;
+  }
+  return r;
+}
+
+// Two's complement nibbles / bytes -> float (exact).
+__device__ __forceinline__ float2 unpack_raw(Raw r, int fmt) {
+  if (fmt == kCI4) {
+    const int b = int(int8_t(uint8_t(r.x)));
+    return make_float2(float(b >> 4), float(int(int8_t(uint8_t(r.x << 4))) >> 4));
+  } else if (fmt == kCI8) {
+    return make_float2(float(int8_t(uint8_t(r.x))), float(int8_t(uint8_t(r.x >> 8))));
+  }
+  return make_float2(__uint_as_float(r.x), __uint_as_float(r.y));
+}
+
+__device__ __forceinline__ float2 load_sample(const uint8_t* row, int a, int fmt) {
+  return unpack_raw(load_raw(row, a, fmt), fmt);
+}
+
+__device__ __forceinline__ void lds_add(float2* p, float2 v) {
+  __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Order LDS traffic of one wavefront: the hardware executes a wave's LDS
+// instructions in order; this keeps the compiler from moving them across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ float2 shfl_xor2(float2 v, int m) {
+  return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+
+template <int N>
+struct Geo {
+  static constexpr int PITCH = N + 2;       // complex values per LDS row
+  static constexpr int FPW = 64 / N;        // frames per wave
+  static constexpr int FRAME = N * PITCH;   // float2 per frame buffer
+  static constexpr int SLOTS = 4 * FPW;     // frames in flight per workgroup
+  static constexpr int LDS = SLOTS * FRAME; // float2 per workgroup
+};
+
+// Gridding schedule ("owner computes"): every nonzero grid cell is owned by
+// exactly one lane of the frame, which sums the cell's kernel contributions
+// w * E'_a (E'_a staged in LDS by the antenna lanes) and stores the cell with
+// a plain LDS write -- no atomics.  The host builds the schedule: per lane a
+// list of slots {cell offset, antenna, weight, first/last-of-cell flags},
+// balanced over lanes.  Cells nobody owns stay zero.
+constexpr int64_t kNoInterval = 0x7fffffffffffffffLL;  // t_cal of a single interval
+constexpr uint32_t kSlotFirst = 1u << 13, kSlotLast = 1u << 14, kSlotOffMask = (1u << 13) - 1;
+
+template <int SM>
+struct SlotTable {
+  uint32_t code[SM];
+  float w[SM];
+  __device__ __forceinline__ void load(const uint2* slots, int S, int L, int lam) {
+    static_for<0, SM>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if (s < S) {
+        const uint2 e = slots[s * L + lam];
+        code[s] = e.x;
+        w[s] = __uint_as_float(e.y);
+      } else {
+        code[s] = 0u;
+        w[s] = 0.f;
+      }
+    });
+  }
+};
+
+// Calibrate (E'_a = u_a E_a) into the frame's E' staging area.
+template <int N, int APL>
+__device__ __forceinline__ void stage_frame(float2* epr, const Raw (&raw)[APL], const float2 (&uu)[APL], int lam,
+                                            int Na, int fmt, bool active) {
+  static_for<0, APL>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int an = lam + N * i;
+    if (an < Na) epr[an] = active ? cmul(unpack_raw(raw[i], fmt), uu[i]) : make_float2(0.f, 0.f);
+  });
+}
+
+// Grid the staged frame into `buf` (owned cells only; the rest stays zero).
+template <int SM>
+__device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const SlotTable<SM>& tab, int S) {
+  float2 acc = make_float2(0.f, 0.f);
+  static_for<0, SM>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    if (s < S) {
+      const uint32_t c = tab.code[s];
+      const float2 e = epr[c >> 16];
+      const float w = tab.w[s];
+      const bool first = (c & kSlotFirst) != 0;
+      acc.x = fmaf(w, e.x, first ? 0.f : acc.x);
+      acc.y = fmaf(w, e.y, first ? 0.f : acc.y);
+      if (c & kSlotLast) buf[c & kSlotOffMask] = acc;
+    }
+  });
+}
+
+template <int N, int APL>
+__device__ __forceinline__ void fetch_frame(Raw (&raw)[APL], float2 (&uu)[APL], const uint8_t* efield,
+                                            const float2* u, int64_t t, int64_t t_cal, int f, int F,
+                                            int Na, int fmt, int lam, bool active) {
+  const int bpe = fmt == kCF32 ? 8 : fmt == kCI8 ? 2 : 1;
+  const uint8_t* row = efield + (t * F + f) * int64_t(Na) * bpe;
+  const float2* urow = u + ((t / t_cal) * F + f) * int64_t(Na);
+  static_for<0, APL>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const int a = lam + N * i;
+    if (active && a < Na) {
+      raw[i] = load_raw(row, a, fmt);
+      uu[i] = urow[a];
+    } else {
+      raw[i] = Raw{0u, 0u};
+      uu[i] = make_float2(0.f, 0.f);
+    }
+  });
+}
+
+// Row FFT -> transpose through LDS -> column FFT.  On entry buf holds the
+// gridded frame; on exit v[ky] = sum_j G_j exp(S 2 pi i j.k / N) for
+// kx = lam, and the lane's buffer row is zero again.
+template <int N, int S>
+__device__ __forceinline__ void transform_frame(float2* buf, float2 (&v)[N], int lam) {
+  constexpr int P = Geo<N>::PITCH;
+  static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = buf[lam * P + decltype(xc)::value]; });
+  fft_reg<N, S>(v);
+  wave_lds_sync();
+  static_for<0, N>([&](auto xc) { buf[decltype(xc)::value * P + lam] = v[decltype(xc)::value]; });
+  wave_lds_sync();
+  static_for<0, N>([&](auto yc) { v[decltype(yc)::value] = buf[lam * P + decltype(yc)::value]; });
+  static_for<0, N>([&](auto yc) { buf[lam * P + decltype(yc)::value] = make_float2(0.f, 0.f); });
+  fft_reg<N, S>(v);
+}
+
+
+// ---------------------------------------------------------------------------
+// EPICal: FP64 update helpers (eq. Cna, eq. damping)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  const double2 n = zmul(a, zconj(b));
+  return make_double2(n.x / d, n.y / d);
+}
+__device__ __forceinline__ double2 zrecip(double2 g) {
+  const double d = g.x * g.x + g.y * g.y;
+  return make_double2(g.x / d, -g.y / d);
+}
+
+// One damped update.  Returns the new gain; sets *st bits if held.
+__device__ __forceinline__ double2 epical_step(double2 Kbar, double Qbar, double2 A, double2 D, double2 g,
+                                               uint8_t hold, double na, double gamma, uint32_t* st) {
+  if (hold) {
+    *st |= (hold & kHoldFlagged ? 1u : 0u) | (hold & kHoldDZero ? 2u : 0u);
+    return g;
+  }
+  // C = Kbar - conj(A) Qbar / (Na conj(g))
+  const double2 t = zdiv(make_double2(A.x * Qbar, -A.y * Qbar), make_double2(na * g.x, -na * g.y));
+  const double2 C = make_double2(Kbar.x - t.x, Kbar.y - t.y);
+  const double2 sol = zdiv(make_double2(C.x * na, C.y * na), D);
+  const double2 gn = make_double2((1.0 - gamma) * sol.x + gamma * g.x, (1.0 - gamma) * sol.y + gamma * g.y);
+  if (!isfinite(gn.x) || !isfinite(gn.y)) {
+    *st |= 4u;
+    return g;
+  }
+  return gn;
+}
+
+
+template <int N, int K2, int APL>
+struct DegridTable {
+  int off[APL][K2];
+  float w[APL][K2];
+  __device__ __forceinline__ void load(const uint32_t* cell_ixy, const float* cell_w, int lam, int Na) {
+    static_for<0, APL>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      const int an = lam + N * i;
+      static_for<0, K2>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (an < Na) {
+          const uint32_t ixy = cell_ixy[an * K2 + k];
+          off[i][k] = int(ixy >> 16) * Geo<N>::PITCH + int(ixy & 0xffffu);
+          w[i][k] = cell_w[an * K2 + k];
+        } else {
+          off[i][k] = 0;
+          w[i][k] = 0.f;
+        }
+      });
+    });
+  }
+};
+
+
+// ---------------------------------------------------------------------------
+// compile-time variants of the N <= 64 engine
+//   APL: antennas per lane of the E' staging (Na <= APL * N)
+//   SM : gridding slots per lane held in registers
+// ---------------------------------------------------------------------------
+inline int apl_for(int N, int na) {
+  const int need = (na + N - 1) / N;
+  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+}
+inline int sm_for(int n_slots) { return n_slots <= 32 ? 32 : n_slots <= 64 ? 64 : 0; }
+
+template <int N, int APL, template <int, int, int> class Launch, typename Args>
+inline hipError_t dispatch_sm(int n_slots, const Args& a, hipStream_t s) {
+  switch (sm_for(n_slots)) {
+    case 32: return Launch<N, APL, 32>::run(a, s);
+    case 64: return Launch<N, APL, 64>::run(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, template <int, int, int> class Launch, typename Args>
+inline hipError_t dispatch_apl(int na, int n_slots, const Args& a, hipStream_t s) {
+  switch (apl_for(N, na)) {
+    case 2: return dispatch_sm<N, 2, Launch>(n_slots, a, s);
+    case 4: return dispatch_sm<N, 4, Launch>(n_slots, a, s);
+    case 8: return dispatch_sm<N, 8, Launch>(n_slots, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <template <int, int, int> class Launch, typename Args>
+inline hipError_t dispatch_n(int N, int na, int n_slots, const Args& a, hipStream_t s) {
+  if (N == 16) return dispatch_apl<16, Launch>(na, n_slots, a, s);
+  if (N == 32) return dispatch_apl<32, Launch>(na, n_slots, a, s);
+  if (N == 64) return dispatch_apl<64, Launch>(na, n_slots, a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace epic

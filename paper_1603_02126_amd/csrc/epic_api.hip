@@ -201,6 +201,60 @@ void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) 
   }
 }
 
+// Owner-computes gridding schedule of the N <= 64 imaging engine: every
+// nonzero cell goes to one lane (greedy balance of contribution counts); each
+// lane gets a list of slots {LDS offset | first | last | antenna << 16, w}.
+// Returns the slot count S; table is [S][L] (lane fastest).
+int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table) {
+  std::vector<int32_t> ix, iy;
+  std::vector<double> w;
+  grid_cells(h, ix, iy, w);
+  std::vector<std::vector<std::pair<int, float>>> cell(size_t(h.nx) * h.ny);
+  for (int a = 0; a < h.na; ++a) {
+    if (h.flag[a]) continue;
+    for (int k = 0; k < h.k2; ++k) {
+      const size_t q = size_t(a) * h.k2 + k;
+      if (w[q] == 0.0) continue;
+      cell[size_t(iy[q]) * h.nx + ix[q]].push_back({a, float(w[q])});
+    }
+  }
+  std::vector<int> order;
+  for (size_t c = 0; c < cell.size(); ++c)
+    if (!cell[c].empty()) order.push_back(int(c));
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cell[x].size() > cell[y].size(); });
+  std::vector<std::vector<int>> lane_cells(L);
+  std::vector<size_t> load(L, 0);
+  for (int c : order) {
+    int best = 0;
+    for (int l = 1; l < L; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_cells[best].push_back(c);
+    load[best] += cell[c].size();
+  }
+  size_t S = 0;
+  for (int l = 0; l < L; ++l) S = std::max(S, load[l]);
+  table.assign(2 * S * L, 0u);
+  for (int l = 0; l < L; ++l) {
+    size_t s = 0;
+    for (int c : lane_cells[l]) {
+      const int cy = c / h.nx, cx = c % h.nx;
+      const uint32_t off = uint32_t(cy * pitch + cx);
+      const auto& lst = cell[c];
+      for (size_t i = 0; i < lst.size(); ++i, ++s) {
+        uint32_t code = off | (uint32_t(lst[i].first) << 16);
+        if (i == 0) code |= 1u << 13;
+        if (i + 1 == lst.size()) code |= 1u << 14;
+        float wf = lst[i].second;
+        uint32_t wb;
+        std::memcpy(&wb, &wf, 4);
+        table[2 * (s * L + l)] = code;
+        table[2 * (s * L + l) + 1] = wb;
+      }
+    }
+  }
+  return int(S);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -210,6 +264,9 @@ struct ArrayPlan {
   HostArray h;
   uint32_t* d_cell_ixy = nullptr;
   float* d_cell_w = nullptr;
+  uint2* d_slots = nullptr;   // gridding schedule of the imaging engine
+  int n_slots = 0;
+  uint8_t* d_flag = nullptr;
   bool has_model = false;
   double gamma = 0;
   int t_cal = 1;
@@ -243,6 +300,8 @@ namespace {
 void free_array(ArrayPlan& p) {
   hipFree(p.d_cell_ixy);
   hipFree(p.d_cell_w);
+  hipFree(p.d_slots);
+  hipFree(p.d_flag);
   hipFree(p.d_k0);
   hipFree(p.d_A);
   hipFree(p.d_D);
@@ -291,8 +350,9 @@ int check_plan(epic_plan_t p, int array) {
 int check_grid_supported(const ArrayPlan& ap) {
   const HostArray& h = ap.h;
   if (h.nx != h.ny) return fail(EPIC_ERR_UNSUPPORTED, "only square grids are implemented (got %d x %d)", h.nx, h.ny);
-  if (!epic::image_supported(h.nx, h.k2, h.na))
-    return fail(EPIC_ERR_UNSUPPORTED, "grid %d with %d antennas is not supported (N in {16,32,64}, Na <= 8N)",
+  if (!epic::image_supported(h.nx, h.na, ap.n_slots))
+    return fail(EPIC_ERR_UNSUPPORTED,
+                "grid %d with %d antennas is not supported (N in {16,32,64}, Na <= 8N, <= 64 cells per lane)",
                 h.nx, h.na);
   return EPIC_OK;
 }
@@ -397,14 +457,25 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
     std::vector<int32_t> ix, iy;
     std::vector<double> w;
     grid_cells(ap.h, ix, iy, w);
-    std::vector<uint32_t> packed(ix.size());
-    std::vector<float> wf(ix.size());
-    for (size_t q = 0; q < ix.size(); ++q) {
-      packed[q] = (uint32_t(iy[q]) << 16) | uint32_t(ix[q]);
-      wf[q] = ap.h.flag[q / ap.h.k2] ? 0.f : float(w[q]);
-    }
+    // device cell tables: four cells per antenna (the nearest-cell kernel is
+    // padded with zero-weight copies of its cell)
+    std::vector<uint32_t> packed(size_t(ap.h.na) * 4);
+    std::vector<float> wf(size_t(ap.h.na) * 4, 0.f);
+    for (int an = 0; an < ap.h.na; ++an)
+      for (int k = 0; k < 4; ++k) {
+        const size_t q = size_t(an) * ap.h.k2 + (ap.h.k2 == 4 ? k : 0);
+        packed[size_t(an) * 4 + k] = (uint32_t(iy[q]) << 16) | uint32_t(ix[q]);
+        wf[size_t(an) * 4 + k] = (ap.h.flag[an] || (ap.h.k2 == 1 && k > 0)) ? 0.f : float(w[q]);
+      }
     int rc = upload(&ap.d_cell_ixy, packed.data(), packed.size());
     if (!rc) rc = upload(&ap.d_cell_w, wf.data(), wf.size());
+    if (!rc) rc = upload(&ap.d_flag, ap.h.flag.data(), ap.h.flag.size());
+    if (!rc && ap.h.nx == ap.h.ny && ap.h.nx <= 64 && ap.h.nx >= 16) {
+      std::vector<uint32_t> tab;
+      const int L = epic::grid_lanes(ap.h.nx);
+      ap.n_slots = build_slots(ap.h, L, epic::grid_pitch(ap.h.nx), tab);
+      rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+    }
     if (rc) {
       epic_plan_destroy(p);
       return rc;
@@ -508,8 +579,8 @@ int epic_grid(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, i
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (nt > 0 && (!efield || !u || !grid)) return fail(EPIC_ERR_ARG, "efield, u and grid must not be NULL");
   epic::GridArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
-                   reinterpret_cast<const float2*>(u), ap.d_cell_ixy, ap.d_cell_w, reinterpret_cast<float2*>(grid)};
-  hipError_t e = epic::launch_grid(ap.h.nx, ap.h.k2, a, static_cast<hipStream_t>(stream));
+                   reinterpret_cast<const float2*>(u), ap.d_slots, ap.n_slots, reinterpret_cast<float2*>(grid)};
+  hipError_t e = epic::launch_grid(ap.h.nx, a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "epic_grid launch");
 }
 
@@ -550,10 +621,10 @@ static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64
   const HostArray& h = ap.h;
   const int N = h.nx;
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
-               ap.d_cell_ixy, ap.d_cell_w, splits, partial};
+               ap.d_slots, ap.n_slots, splits, partial};
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s);
-    hipError_t e = epic::launch_image(N, h.k2, ia, s);
+    hipError_t e = epic::launch_image(N, ia, s);
     if (e != hipSuccess) return hip_fail(e, "imaging launch");
   }
   {
@@ -578,6 +649,8 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     ArrayPlan& ap = plan->arrays[i];
     if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", i);
     if ((rc = check_grid_supported(ap))) return rc;
+    if (!epic::solve_supported(ap.h.na, ap.h.efmt))
+      return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
     const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
     const int splits = pick_splits(plan, ap.h.F, n_samples, slots_for(ap.h.nx));
@@ -614,35 +687,60 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   return EPIC_OK;
 }
 
-int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const float* u, float* image,
-               epic_stream_t stream) {
+int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const double* gains,
+               float* image, epic_stream_t stream) {
   int rc = check_plan(plan, array);
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
   if ((rc = check_grid_supported(ap))) return rc;
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
-  if (!efield || !u || !image) return fail(EPIC_ERR_ARG, "efield, u and image must not be NULL");
+  if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image must not be NULL");
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
-  const int splits = pick_splits(plan, ap.h.F, n_samples, slots_for(ap.h.nx));
+  const HostArray& h = ap.h;
+  const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+  const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
-  rc = scratch(plan, size_t(splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float), &scr);
+  rc = scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
   if (rc) return rc;
-  return image_pass(plan, ap, efield, n_samples, reinterpret_cast<const float2*>(u),
-                    std::numeric_limits<int64_t>::max(), image, static_cast<hipStream_t>(stream),
-                    static_cast<float*>(scr), splits);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* u = static_cast<float2*>(scr);
+  hipError_t e = epic::launch_recip(reinterpret_cast<const double2*>(gains), ap.d_flag, h.F, h.na, u, s);
+  if (e != hipSuccess) return hip_fail(e, "reciprocal launch");
+  return image_pass(plan, ap, efield, n_samples, u, std::numeric_limits<int64_t>::max(), image, s,
+                    reinterpret_cast<float*>(static_cast<char*>(scr) + ub), splits);
 }
 
 int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const double* gains,
                        const float* dL_dI, double* dL_dg, epic_stream_t stream) {
-  (void)efield;
-  (void)n_samples;
-  (void)gains;
-  (void)dL_dI;
-  (void)dL_dg;
-  (void)stream;
   int rc = check_plan(plan, array);
   if (rc) return rc;
-  return fail(EPIC_ERR_UNSUPPORTED, "epic_image_adjoint is not implemented yet");
+  ArrayPlan& ap = plan->arrays[array];
+  if ((rc = check_grid_supported(ap))) return rc;
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  if (!efield || !gains || !dL_dI || !dL_dg) return fail(EPIC_ERR_ARG, "efield, gains, dL_dI and dL_dg must not be NULL");
+  if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
+  const HostArray& h = ap.h;
+  const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+  const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
+  void* scr = nullptr;
+  rc = scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* u = static_cast<float2*>(scr);
+  double2* partial = reinterpret_cast<double2*>(static_cast<char*>(scr) + ub);
+  hipError_t e = epic::launch_recip(reinterpret_cast<const double2*>(gains), ap.d_flag, h.F, h.na, u, s);
+  if (e != hipSuccess) return hip_fail(e, "reciprocal launch");
+  epic::AdjointArgs a{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, dL_dI, ap.d_slots,
+                      ap.n_slots, ap.d_cell_ixy, ap.d_cell_w, h.k2, splits, partial};
+  {
+    Timed tm(plan, EPIC_TIMER_ADJOINT, s);
+    e = epic::launch_adjoint(h.nx, a, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  }
+  const double scale = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
+  e = epic::launch_adjoint_reduce(partial, splits, h.F, h.na, reinterpret_cast<const double2*>(gains), scale,
+                                  reinterpret_cast<double2*>(dL_dg), s);
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "adjoint reduction launch");
 }
 
 }  // extern "C"

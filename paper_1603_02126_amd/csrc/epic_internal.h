@@ -22,8 +22,8 @@ struct ImageArgs {
   int F, Na, fmt;
   const float2* u;          // [n_int][F][Na]: u of interval t / t_cal
   int64_t t_cal;
-  const uint32_t* cell_ixy; // [Na][K2] (iy << 16) | ix
-  const float* cell_w;      // [Na][K2] (0 for flagged antennas)
+  const uint2* slots;       // gridding schedule [n_slots][lanes]
+  int n_slots;
   int splits;               // workgroups per channel
   float* partial;           // [splits][F][N*N]
 };
@@ -34,8 +34,8 @@ struct GridArgs {
   int64_t t0;
   int nt, F, Na, fmt;
   const float2* u;          // [F][Na]
-  const uint32_t* cell_ixy;
-  const float* cell_w;
+  const uint2* slots;
+  int n_slots;
   float2* grid;             // [nt][F][N][N]
 };
 
@@ -89,24 +89,34 @@ struct AdjointArgs {
   int F, Na, fmt;
   const float2* u;          // [F][Na]
   const float* R;           // [F][N][N] dL/dI
-  const uint32_t* cell_ixy;
+  const uint2* slots;
+  int n_slots;
+  const uint32_t* cell_ixy; // [Na][K2]
   const float* cell_w;
+  int k2;
   int splits;
-  float2* partial;          // [splits][F][Na] sum_t conj(E) * degrid(...)
+  double2* partial;         // [splits][F][Na]
 };
 
 // Launchers: return hipSuccess or the launch error.  N = grid size.
-bool image_supported(int N, int k2, int na);
-hipError_t launch_image(int N, int k2, const ImageArgs& a, hipStream_t s);
-hipError_t launch_grid(int N, int k2, const GridArgs& a, hipStream_t s);
+// Gridding schedule geometry of the N <= 64 engine: lanes per frame and LDS
+// row pitch (complex values) that slot offsets refer to.
+int grid_lanes(int N);
+int grid_pitch(int N);
+bool image_supported(int N, int na, int n_slots);
+hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);
+hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);
 hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
                          float* image, hipStream_t s);
+bool solve_supported(int na, int fmt);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
-hipError_t launch_adjoint(int N, int k2, const AdjointArgs& a, hipStream_t s);
-hipError_t launch_adjoint_reduce(const float2* partial, int splits, int F, int Na,
+hipError_t launch_adjoint(int N, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_adjoint_reduce(const double2* partial, int splits, int F, int Na,
                                  const double2* gains, double scale, double2* dL_dg,
                                  hipStream_t s);
+hipError_t launch_recip(const double2* gains, const uint8_t* flag, int F, int Na, float2* u,
+                        hipStream_t s);
 
 }  // namespace epic

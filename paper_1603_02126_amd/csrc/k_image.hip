@@ -1,0 +1,255 @@
+// HIP kernels (gfx950) for the EPIC direct-imaging loop with EPICal.
+//
+// Layout of the imaging engine ("one lane = one pencil"): a wave64 owns
+// 64 / N frames of an N x N grid (N <= 64); lane lam of a frame owns grid row
+// lam.  Per frame:
+//   1. calibrate + grid (Sec. 2.1, E'_a = E_a / g_a and eq. gridding): each
+//      lane takes antennas lam, lam + N, ... and scatters w * u * E with LDS
+//      float atomics into the frame's zeroed LDS buffer;
+//   2. lane lam loads row lam into registers and runs an N-point FFT there;
+//   3. the row spectrum is written transposed to LDS (lane-consecutive
+//      addresses, conflict free) and lane lam reads back column lam (rows of
+//      the buffer are padded by two complex values to spread banks), zeroing
+//      the buffer for the next frame as it goes;
+//   4. an N-point FFT over the other axis gives X(kx = lam, ky), whose |X|^2
+//      is accumulated in registers over all frames of the wave (squaring and
+//      time averaging, Sec. 2.1).
+// Waves of one workgroup share a channel and split its samples; their
+// accumulators are summed through LDS into one partial image per workgroup.
+//
+// The calibration solve runs in its own kernel before imaging: the tapped
+// pixel of interval n only needs the gains of interval n, and its value
+// X_t(k0) equals the beamformed sum (1/Na) sum_a A_a(k0) u_a E_a(t) (the
+// transform of the gridded field evaluated at one pixel), so the feedback
+// recursion costs O(Na) per sample and the O(Ng log Ng) imaging of every
+// sample becomes independent work.
+#include "engine.h"
+
+namespace epic {
+
+// ---------------------------------------------------------------------------
+// Fused imaging kernel
+// ---------------------------------------------------------------------------
+template <int N, int APL, int SM>
+__global__ __launch_bounds__(256) void k_image(ImageArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS];
+  __shared__ float2 lds_e[G::SLOTS * APL * N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane / N, lam = lane % N;
+  const int slot = wave * G::FPW + h;
+  const int f = blockIdx.x % a.F;
+  const int s = blockIdx.x / a.F;
+  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
+  float2* buf = lds + slot * G::FRAME;
+  float2* epr = lds_e + slot * (APL * N);
+
+  SlotTable<SM> tab;
+  tab.load(a.slots, a.n_slots, N, lam);
+  static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = make_float2(0.f, 0.f); });
+
+  float acc[N];
+  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+
+  const int64_t iters = (te - tb + G::SLOTS - 1) / G::SLOTS;
+  Raw raw[APL];
+  float2 uu[APL];
+  {
+    const int64_t t = tb + slot;
+    fetch_frame<N, APL>(raw, uu, a.efield, a.u, t, a.t_cal, f, a.F, a.Na, a.fmt, lam, t < te);
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t t = tb + it * G::SLOTS + slot;
+    stage_frame<N, APL>(epr, raw, uu, lam, a.Na, a.fmt, t < te);
+    {
+      const int64_t tn = t + G::SLOTS;
+      fetch_frame<N, APL>(raw, uu, a.efield, a.u, tn, a.t_cal, f, a.F, a.Na, a.fmt, lam, tn < te);
+    }
+    wave_lds_sync();
+    grid_frame<SM>(buf, epr, tab, a.n_slots);
+    wave_lds_sync();
+    float2 v[N];
+    transform_frame<N, +1>(buf, v, lam);
+    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+  }
+
+  // workgroup reduction of the SLOTS accumulators
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+  static_for<0, N>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    red[(slot * N + y) * N + lam] = acc[y];
+  });
+  __syncthreads();
+  float* out = a.partial + (int64_t(s) * a.F + f) * (N * N);
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    float sum = 0.f;
+#pragma unroll
+    for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];
+    out[idx] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage-wise gridding to HBM (one frame per lane group; tables read from
+// memory: this is the debugging path, not the timed one)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_grid(GridArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS];
+  __shared__ float2 lds_e[G::SLOTS * 8 * N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane / N, lam = lane % N;
+  const int slot = wave * G::FPW + h;
+  const int64_t q = int64_t(blockIdx.x) * G::SLOTS + slot;  // frame = t * F + f
+  const bool active = q < int64_t(a.nt) * a.F;
+  float2* buf = lds + slot * G::FRAME;
+  float2* epr = lds_e + slot * (8 * N);
+  static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  const int64_t t = active ? q / a.F : 0;
+  const int f = active ? int(q % a.F) : 0;
+  const int bpe = efmt_bytes(a.fmt);
+  const uint8_t* row = a.efield + ((a.t0 + t) * a.F + f) * int64_t(a.Na) * bpe;
+  for (int an = lam; an < a.Na; an += N)
+    epr[an] = active ? cmul(load_sample(row, an, a.fmt), a.u[int64_t(f) * a.Na + an]) : make_float2(0.f, 0.f);
+  wave_lds_sync();
+  float2 acc = make_float2(0.f, 0.f);
+  for (int s = 0; s < a.n_slots; ++s) {
+    const uint2 e = a.slots[s * N + lam];
+    const float2 ev = epr[e.x >> 16];
+    const float w = __uint_as_float(e.y);
+    const bool first = (e.x & kSlotFirst) != 0;
+    acc.x = fmaf(w, ev.x, first ? 0.f : acc.x);
+    acc.y = fmaf(w, ev.y, first ? 0.f : acc.y);
+    if (e.x & kSlotLast) buf[e.x & kSlotOffMask] = acc;
+  }
+  wave_lds_sync();
+  if (active) {
+    float2* out = a.grid + q * (N * N);
+    static_for<0, N>([&](auto yc) {
+      constexpr int y = decltype(yc)::value;
+      out[y * N + lam] = buf[y * G::PITCH + lam];
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage-wise transform + square + accumulate (+ tap) from HBM grids
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_image_acc(ImageAccArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane / N, lam = lane % N;
+  const int slot = wave * G::FPW + h;
+  const int f = blockIdx.x;
+  float2* buf = lds + slot * G::FRAME;
+  const int kx0 = a.k0 ? a.k0[2 * f] : 0, ky0 = a.k0 ? a.k0[2 * f + 1] : 0;
+  float acc[N];
+  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  const int iters = (a.nt + G::SLOTS - 1) / G::SLOTS;
+  for (int it = 0; it < iters; ++it) {
+    const int t = it * G::SLOTS + slot;
+    const bool active = t < a.nt;
+    float2 v[N];
+    const float2* row = a.grid + ((int64_t(active ? t : 0) * a.F + f) * N + lam) * N;
+    static_for<0, N>([&](auto xc) {
+      constexpr int x = decltype(xc)::value;
+      v[x] = active ? row[x] : make_float2(0.f, 0.f);
+    });
+    wave_lds_sync();
+    static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = v[decltype(xc)::value]; });
+    wave_lds_sync();
+    transform_frame<N, +1>(buf, v, lam);
+    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    if (a.tap && active && lam == kx0) {
+      float2 p = make_float2(0.f, 0.f);
+      static_for<0, N>([&](auto yc) {
+        if (decltype(yc)::value == ky0) p = v[decltype(yc)::value];
+      });
+      a.tap[int64_t(t) * a.F + f] = cscale(p, a.inv_na);
+    }
+  }
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+  static_for<0, N>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    red[(slot * N + y) * N + lam] = acc[y];
+  });
+  __syncthreads();
+  const float s2 = a.inv_na * a.inv_na;
+  float* img = a.image + int64_t(f) * N * N;
+  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    float sum = 0.f;
+#pragma unroll
+    for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];
+    img[idx] += sum * s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Partial-image reduction (FP64 sum over splits)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(const float* partial, int splits, int64_t per_split,
+                                                double scale, float* image) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= per_split) return;
+  double s = 0.0;
+  for (int k = 0; k < splits; ++k) s += double(partial[int64_t(k) * per_split + i]);
+  image[i] = float(s * scale);
+}
+
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int grid_lanes(int N) { return N; }
+int grid_pitch(int N) { return N + 2; }
+
+bool image_supported(int N, int na, int n_slots) {
+  return (N == 16 || N == 32 || N == 64) && na <= 8 * N && apl_for(N, na) != 0 && sm_for(n_slots) != 0;
+}
+
+template <int N, int APL, int SM>
+struct LaunchImage {
+  static hipError_t run(const ImageArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_image<N, APL, SM>), dim3(a.F * a.splits), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
+  return dispatch_n<LaunchImage>(N, a.Na, a.n_slots, a, s);
+}
+
+hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s) {
+  if (a.nt == 0) return hipSuccess;
+  const int64_t frames = int64_t(a.nt) * a.F;
+  const int slots = 4 * (64 / N);
+  const dim3 grid(unsigned((frames + slots - 1) / slots));
+  if (N == 16) hipLaunchKernelGGL((k_grid<16>), grid, dim3(256), 0, s, a);
+  else if (N == 32) hipLaunchKernelGGL((k_grid<32>), grid, dim3(256), 0, s, a);
+  else if (N == 64) hipLaunchKernelGGL((k_grid<64>), grid, dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s) {
+  if (a.nt == 0) return hipSuccess;
+  if (N == 16) hipLaunchKernelGGL((k_image_acc<16>), dim3(a.F), dim3(256), 0, s, a);
+  else if (N == 32) hipLaunchKernelGGL((k_image_acc<32>), dim3(a.F), dim3(256), 0, s, a);
+  else if (N == 64) hipLaunchKernelGGL((k_image_acc<64>), dim3(a.F), dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale, float* image,
+                         hipStream_t s) {
+  const int64_t blocks = (per_split + 255) / 256;
+  hipLaunchKernelGGL(k_reduce, dim3(unsigned(blocks)), dim3(256), 0, s, partial, splits, per_split, scale,
+                     image);
+  return hipGetLastError();
+}
+
+}  // namespace epic

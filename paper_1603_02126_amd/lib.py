@@ -339,20 +339,22 @@ class Plan:
         keep += [a_e, a_g, a_i, a_h, a_s]
         _check(load().epic_run(self._h, a_e, int(n_samples), a_g, a_i, a_h, a_s, _stream(stream)))
 
-    def image(self, i, efield, n_samples, u, out=None, stream=None):
+    def image(self, i, efield, n_samples, gains, out=None, stream=None):
+        """epic_image: time-averaged image with fixed gains [F, Na] complex128."""
         torch = _torch()
         F, Na, ny, nx = self._dims(i)
         pe, T = self._efield(i, efield)
         if T < n_samples:
             raise ValueError("n_samples exceeds the E-field stream")
-        pu = _req(u, torch.complex64, (F, Na), "u", self.device)
+        pg = _req(gains, torch.complex128, (F, Na), "gains", self.device)
         if out is None:
             out = torch.empty((F, ny, nx), dtype=torch.float32, device=self.device)
         po = _req(out, torch.float32, (F, ny, nx), "image", self.device)
-        _check(load().epic_image(self._h, i, pe, int(n_samples), pu, po, _stream(stream)))
+        _check(load().epic_image(self._h, i, pe, int(n_samples), pg, po, _stream(stream)))
         return out
 
     def image_adjoint(self, i, efield, n_samples, gains, dL_dI, out=None, stream=None):
+        """epic_image_adjoint: dL/dRe g + i dL/dIm g for a real loss of the image."""
         torch = _torch()
         F, Na, ny, nx = self._dims(i)
         pe, T = self._efield(i, efield)

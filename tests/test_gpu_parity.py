@@ -209,8 +209,7 @@ def test_fixed_gain_image(cuda):
     packed = synth.make_efield(wl)
     g = synth.random_gains(3, 2, a.n_ant)
     with _lib().Plan([a]) as plan:
-        img = plan.image(0, torch.from_numpy(packed).to(cuda), 77,
-                         torch.from_numpy((1 / g).astype(np.complex64)).to(cuda)).cpu().numpy()
+        img = plan.image(0, torch.from_numpy(packed).to(cuda), 77, torch.from_numpy(g).to(cuda)).cpu().numpy()
     cells = O.grid_cells(a.ant_xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
     E = O.unpack(packed, a.efmt)
     u32 = (1 / g).astype(np.complex64).astype(np.complex128)

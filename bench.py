@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--workload", default="lwa")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after timing, run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -161,6 +163,13 @@ def main():
     tim = plan.timing()
     plan.set_option(lib.OPT_TIMING, 0)
     print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy reference: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+        del src, dst
 
     frames = a.n_chan * wl.n_samples
     ms_step = dt / args.steps * 1e3

@@ -75,30 +75,21 @@ struct Geo {
 // Gridding schedule ("owner computes"): every nonzero grid cell is owned by
 // exactly one lane of the frame, which sums the cell's kernel contributions
 // w * E'_a (E'_a staged in LDS by the antenna lanes) and stores the cell with
-// a plain LDS write -- no atomics.  The host builds the schedule: per lane a
-// list of slots {cell offset, antenna, weight, first/last-of-cell flags},
-// balanced over lanes.  Cells nobody owns stay zero.
+// a plain LDS write -- no atomics.  The host builds the schedule, balanced
+// over lanes: per lane a list of slots (lane fastest in memory), each
+//   code = antenna | cell offset << 12 | first-of-cell << 31,  weight (float)
+// A lane's slots of one cell are consecutive; every slot stores the running
+// sum, so the cell's last slot leaves the full sum.  Padding slots have zero
+// weight and store into a pad column that the transform never reads.  Cells
+// nobody owns stay zero.  The table lives in LDS, shared by the workgroup.
 constexpr int64_t kNoInterval = 0x7fffffffffffffffLL;  // t_cal of a single interval
-constexpr uint32_t kSlotFirst = 1u << 13, kSlotLast = 1u << 14, kSlotOffMask = (1u << 13) - 1;
+constexpr uint32_t kSlotAntMask = 0xfffu, kSlotCellShift = 12, kSlotCellMask = 0x1fffu;
+constexpr int kLdsBytes = 163840 - 1024;                // LDS per workgroup on gfx950, minus a margin
 
-template <int SM>
-struct SlotTable {
-  uint32_t code[SM];
-  float w[SM];
-  __device__ __forceinline__ void load(const uint2* slots, int S, int L, int lam) {
-    static_for<0, SM>([&](auto sc) {
-      constexpr int s = decltype(sc)::value;
-      if (s < S) {
-        const uint2 e = slots[s * L + lam];
-        code[s] = e.x;
-        w[s] = __uint_as_float(e.y);
-      } else {
-        code[s] = 0u;
-        w[s] = 0.f;
-      }
-    });
-  }
-};
+// Copy the slot table (S x L entries) into LDS with the whole workgroup.
+__device__ __forceinline__ void load_slot_table(uint2* stab, const uint2* slots, int S, int L) {
+  for (int i = threadIdx.x; i < S * L; i += blockDim.x) stab[i] = slots[i];
+}
 
 // Calibrate (E'_a = u_a E_a) into the frame's E' staging area.
 template <int N, int APL>
@@ -112,21 +103,19 @@ __device__ __forceinline__ void stage_frame(float2* epr, const Raw (&raw)[APL], 
 }
 
 // Grid the staged frame into `buf` (owned cells only; the rest stays zero).
-template <int SM>
-__device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const SlotTable<SM>& tab, int S) {
+__device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const uint2* stab, int S, int L,
+                                           int lam) {
   float2 acc = make_float2(0.f, 0.f);
-  static_for<0, SM>([&](auto sc) {
-    constexpr int s = decltype(sc)::value;
-    if (s < S) {
-      const uint32_t c = tab.code[s];
-      const float2 e = epr[c >> 16];
-      const float w = tab.w[s];
-      const bool first = (c & kSlotFirst) != 0;
-      acc.x = fmaf(w, e.x, first ? 0.f : acc.x);
-      acc.y = fmaf(w, e.y, first ? 0.f : acc.y);
-      if (c & kSlotLast) buf[c & kSlotOffMask] = acc;
-    }
-  });
+#pragma unroll 4
+  for (int s = 0; s < S; ++s) {
+    const uint2 e = stab[s * L + lam];
+    const float2 ev = epr[e.x & kSlotAntMask];
+    const float w = __uint_as_float(e.y);
+    const bool first = int(e.x) < 0;
+    acc.x = fmaf(w, ev.x, first ? 0.f : acc.x);
+    acc.y = fmaf(w, ev.y, first ? 0.f : acc.y);
+    buf[(e.x >> kSlotCellShift) & kSlotCellMask] = acc;
+  }
 }
 
 template <int N, int APL>
@@ -230,38 +219,50 @@ struct DegridTable {
 // ---------------------------------------------------------------------------
 // compile-time variants of the N <= 64 engine
 //   APL: antennas per lane of the E' staging (Na <= APL * N)
-//   SM : gridding slots per lane held in registers
+// LDS budget per workgroup: frame buffers, E' staging, then the slot table.
 // ---------------------------------------------------------------------------
+template <int N, int APL>
+struct Budget {
+  static constexpr int FRAMES = Geo<N>::LDS * 8;
+  static constexpr int STAGE = Geo<N>::SLOTS * APL * N * 8;
+  static constexpr int TAB_SLOTS = (kLdsBytes - FRAMES - STAGE) / (N * 8);   // slot rows that fit
+};
+
 inline int apl_for(int N, int na) {
   const int need = (na + N - 1) / N;
   return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
 }
-inline int sm_for(int n_slots) { return n_slots <= 32 ? 32 : n_slots <= 64 ? 64 : 0; }
 
-template <int N, int APL, template <int, int, int> class Launch, typename Args>
-inline hipError_t dispatch_sm(int n_slots, const Args& a, hipStream_t s) {
-  switch (sm_for(n_slots)) {
-    case 32: return Launch<N, APL, 32>::run(a, s);
-    case 64: return Launch<N, APL, 64>::run(a, s);
-    default: return hipErrorInvalidValue;
+inline int tab_slots_for(int N, int apl) {
+  switch (N * 16 + apl) {
+    case 16 * 16 + 2: return Budget<16, 2>::TAB_SLOTS;
+    case 16 * 16 + 4: return Budget<16, 4>::TAB_SLOTS;
+    case 16 * 16 + 8: return Budget<16, 8>::TAB_SLOTS;
+    case 32 * 16 + 2: return Budget<32, 2>::TAB_SLOTS;
+    case 32 * 16 + 4: return Budget<32, 4>::TAB_SLOTS;
+    case 32 * 16 + 8: return Budget<32, 8>::TAB_SLOTS;
+    case 64 * 16 + 2: return Budget<64, 2>::TAB_SLOTS;
+    case 64 * 16 + 4: return Budget<64, 4>::TAB_SLOTS;
+    case 64 * 16 + 8: return Budget<64, 8>::TAB_SLOTS;
+    default: return 0;
   }
 }
 
-template <int N, template <int, int, int> class Launch, typename Args>
-inline hipError_t dispatch_apl(int na, int n_slots, const Args& a, hipStream_t s) {
+template <int N, template <int, int> class Launch, typename Args>
+inline hipError_t dispatch_apl(int na, const Args& a, hipStream_t s) {
   switch (apl_for(N, na)) {
-    case 2: return dispatch_sm<N, 2, Launch>(n_slots, a, s);
-    case 4: return dispatch_sm<N, 4, Launch>(n_slots, a, s);
-    case 8: return dispatch_sm<N, 8, Launch>(n_slots, a, s);
+    case 2: return Launch<N, 2>::run(a, s);
+    case 4: return Launch<N, 4>::run(a, s);
+    case 8: return Launch<N, 8>::run(a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <template <int, int, int> class Launch, typename Args>
-inline hipError_t dispatch_n(int N, int na, int n_slots, const Args& a, hipStream_t s) {
-  if (N == 16) return dispatch_apl<16, Launch>(na, n_slots, a, s);
-  if (N == 32) return dispatch_apl<32, Launch>(na, n_slots, a, s);
-  if (N == 64) return dispatch_apl<64, Launch>(na, n_slots, a, s);
+template <template <int, int> class Launch, typename Args>
+inline hipError_t dispatch_n(int N, int na, const Args& a, hipStream_t s) {
+  if (N == 16) return dispatch_apl<16, Launch>(na, a, s);
+  if (N == 32) return dispatch_apl<32, Launch>(na, a, s);
+  if (N == 64) return dispatch_apl<64, Launch>(na, a, s);
   return hipErrorInvalidValue;
 }
 

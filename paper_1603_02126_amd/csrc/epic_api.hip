@@ -203,8 +203,10 @@ void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) 
 
 // Owner-computes gridding schedule of the N <= 64 imaging engine: every
 // nonzero cell goes to one lane (greedy balance of contribution counts); each
-// lane gets a list of slots {LDS offset | first | last | antenna << 16, w}.
-// Returns the slot count S; table is [S][L] (lane fastest).
+// lane gets consecutive slots per owned cell, coded
+//   antenna | LDS cell offset << 12 | first-of-cell << 31,  weight bits.
+// Padding slots store zero into the pad column (offset = grid size).
+// Returns the slot count S; table is [S][L] (lane fastest), 2 words each.
 int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
@@ -233,6 +235,7 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
   }
   size_t S = 0;
   for (int l = 0; l < L; ++l) S = std::max(S, load[l]);
+  const uint32_t pad = uint32_t(h.nx) << 12;   // row 0, first pad column
   table.assign(2 * S * L, 0u);
   for (int l = 0; l < L; ++l) {
     size_t s = 0;
@@ -241,15 +244,18 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
       const uint32_t off = uint32_t(cy * pitch + cx);
       const auto& lst = cell[c];
       for (size_t i = 0; i < lst.size(); ++i, ++s) {
-        uint32_t code = off | (uint32_t(lst[i].first) << 16);
-        if (i == 0) code |= 1u << 13;
-        if (i + 1 == lst.size()) code |= 1u << 14;
+        uint32_t code = uint32_t(lst[i].first) | (off << 12);
+        if (i == 0) code |= 1u << 31;
         float wf = lst[i].second;
         uint32_t wb;
         std::memcpy(&wb, &wf, 4);
         table[2 * (s * L + l)] = code;
         table[2 * (s * L + l) + 1] = wb;
       }
+    }
+    for (; s < S; ++s) {
+      table[2 * (s * L + l)] = pad | (1u << 31);
+      table[2 * (s * L + l) + 1] = 0u;
     }
   }
   return int(S);

@@ -12,12 +12,13 @@ namespace epic {
 //   partial_a += conj(E_a(t)) sum_k w_ak DFT-(R . DFT+(G_t))[cell_ak]
 // The host-side reduction applies 2 conj(-1/g^2) / (T Na^2).
 // ---------------------------------------------------------------------------
-template <int N, int APL, int SM>
+template <int N, int APL>
 __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
   using G = Geo<N>;
   constexpr int P = G::PITCH;
   __shared__ float2 lds[G::LDS];
   __shared__ float2 lds_e[G::SLOTS * APL * N];
+  __shared__ uint2 stab[Budget<N, APL>::TAB_SLOTS * N];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane / N, lam = lane % N;
   const int slot = wave * G::FPW + h;
@@ -27,8 +28,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
   float2* buf = lds + slot * G::FRAME;
   float2* epr = lds_e + slot * (APL * N);
 
-  SlotTable<SM> tab;
-  tab.load(a.slots, a.n_slots, N, lam);
+  load_slot_table(stab, a.slots, a.n_slots, N);
   constexpr int K2 = 4;  // device cell tables are padded to four cells
   DegridTable<N, K2, APL> dg;
   dg.load(a.cell_ixy, a.cell_w, lam, a.Na);
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
     r[y] = a.R[(int64_t(f) * N + y) * N + lam];
   });
   static_for<0, N>([&](auto xc) { buf[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  __syncthreads();
   double2 du[APL];
   static_for<0, APL>([&](auto ic) { du[decltype(ic)::value] = make_double2(0.0, 0.0); });
 
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
       fetch_frame<N, APL>(raw, uu, a.efield, a.u, tn, kNoInterval, f, a.F, a.Na, a.fmt, lam, tn < te);
     }
     wave_lds_sync();
-    grid_frame<SM>(buf, epr, tab, a.n_slots);
+    grid_frame(buf, epr, stab, a.n_slots, N, lam);
     wave_lds_sync();
     float2 v[N];
     transform_frame<N, +1>(buf, v, lam);
@@ -140,15 +141,15 @@ __global__ __launch_bounds__(256) void k_recip(const double2* gains, const uint8
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int N, int APL, int SM>
+template <int N, int APL>
 struct LaunchAdjoint {
   static hipError_t run(const AdjointArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_adjoint<N, APL, SM>), dim3(a.F * a.splits), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_adjoint<N, APL>), dim3(a.F * a.splits), dim3(256), 0, s, a);
     return hipGetLastError();
   }
 };
 hipError_t launch_adjoint(int N, const AdjointArgs& a, hipStream_t s) {
-  return dispatch_n<LaunchAdjoint>(N, a.Na, a.n_slots, a, s);
+  return dispatch_n<LaunchAdjoint>(N, a.Na, a, s);
 }
 hipError_t launch_adjoint_reduce(const double2* partial, int splits, int F, int Na, const double2* gains,
                                  double scale, double2* dL_dg, hipStream_t s) {

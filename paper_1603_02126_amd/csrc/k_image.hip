@@ -30,11 +30,12 @@ namespace epic {
 // ---------------------------------------------------------------------------
 // Fused imaging kernel
 // ---------------------------------------------------------------------------
-template <int N, int APL, int SM>
+template <int N, int APL>
 __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS];
   __shared__ float2 lds_e[G::SLOTS * APL * N];
+  __shared__ uint2 stab[Budget<N, APL>::TAB_SLOTS * N];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane / N, lam = lane % N;
   const int slot = wave * G::FPW + h;
@@ -44,9 +45,9 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   float2* buf = lds + slot * G::FRAME;
   float2* epr = lds_e + slot * (APL * N);
 
-  SlotTable<SM> tab;
-  tab.load(a.slots, a.n_slots, N, lam);
+  load_slot_table(stab, a.slots, a.n_slots, N);
   static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  __syncthreads();
 
   float acc[N];
   static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
       fetch_frame<N, APL>(raw, uu, a.efield, a.u, tn, a.t_cal, f, a.F, a.Na, a.fmt, lam, tn < te);
     }
     wave_lds_sync();
-    grid_frame<SM>(buf, epr, tab, a.n_slots);
+    grid_frame(buf, epr, stab, a.n_slots, N, lam);
     wave_lds_sync();
     float2 v[N];
     transform_frame<N, +1>(buf, v, lam);
@@ -114,16 +115,7 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs a) {
   for (int an = lam; an < a.Na; an += N)
     epr[an] = active ? cmul(load_sample(row, an, a.fmt), a.u[int64_t(f) * a.Na + an]) : make_float2(0.f, 0.f);
   wave_lds_sync();
-  float2 acc = make_float2(0.f, 0.f);
-  for (int s = 0; s < a.n_slots; ++s) {
-    const uint2 e = a.slots[s * N + lam];
-    const float2 ev = epr[e.x >> 16];
-    const float w = __uint_as_float(e.y);
-    const bool first = (e.x & kSlotFirst) != 0;
-    acc.x = fmaf(w, ev.x, first ? 0.f : acc.x);
-    acc.y = fmaf(w, ev.y, first ? 0.f : acc.y);
-    if (e.x & kSlotLast) buf[e.x & kSlotOffMask] = acc;
-  }
+  grid_frame(buf, epr, a.slots, a.n_slots, N, lam);
   wave_lds_sync();
   if (active) {
     float2* out = a.grid + q * (N * N);
@@ -209,19 +201,21 @@ int grid_lanes(int N) { return N; }
 int grid_pitch(int N) { return N + 2; }
 
 bool image_supported(int N, int na, int n_slots) {
-  return (N == 16 || N == 32 || N == 64) && na <= 8 * N && apl_for(N, na) != 0 && sm_for(n_slots) != 0;
+  if (!(N == 16 || N == 32 || N == 64) || na > 8 * N) return false;
+  const int apl = apl_for(N, na);
+  return apl != 0 && n_slots <= tab_slots_for(N, apl);
 }
 
-template <int N, int APL, int SM>
+template <int N, int APL>
 struct LaunchImage {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_image<N, APL, SM>), dim3(a.F * a.splits), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_image<N, APL>), dim3(a.F * a.splits), dim3(256), 0, s, a);
     return hipGetLastError();
   }
 };
 
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
-  return dispatch_n<LaunchImage>(N, a.Na, a.n_slots, a, s);
+  return dispatch_n<LaunchImage>(N, a.Na, a, s);
 }
 
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s) {

@@ -261,6 +261,63 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
   return int(S);
 }
 
+// Gridding schedule of the residue-class engine (N = 64 R): contributions are
+// grouped by sub-cell q = j mod 64 and sub-cells are balanced over 64 lanes;
+// each slot keeps the full cell j = 64 p + q so that the kernel can apply the
+// class phase exp(+2 pi i j.c / N).
+int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table) {
+  std::vector<int32_t> ix, iy;
+  std::vector<double> w;
+  grid_cells(h, ix, iy, w);
+  struct Contrib { int a, jx, jy; float w; };
+  std::vector<std::vector<Contrib>> sub(64 * 64);
+  for (int a = 0; a < h.na; ++a) {
+    if (h.flag[a]) continue;
+    for (int k = 0; k < h.k2; ++k) {
+      const size_t q = size_t(a) * h.k2 + k;
+      if (w[q] == 0.0) continue;
+      sub[size_t(iy[q] % 64) * 64 + ix[q] % 64].push_back({a, ix[q], iy[q], float(w[q])});
+    }
+  }
+  std::vector<int> order;
+  for (int c = 0; c < 64 * 64; ++c)
+    if (!sub[c].empty()) order.push_back(c);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sub[x].size() > sub[y].size(); });
+  std::vector<std::vector<int>> lane_cells(64);
+  std::vector<size_t> load(64, 0);
+  for (int c : order) {
+    int best = 0;
+    for (int l = 1; l < 64; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_cells[best].push_back(c);
+    load[best] += sub[c].size();
+  }
+  size_t S = 0;
+  for (int l = 0; l < 64; ++l) S = std::max(S, load[l]);
+  table.assign(2 * S * 64, 0u);
+  for (int l = 0; l < 64; ++l) {
+    size_t s = 0;
+    for (int c : lane_cells[l]) {
+      const auto& lst = sub[c];
+      for (size_t i = 0; i < lst.size(); ++i, ++s) {
+        const Contrib& q = lst[i];
+        uint32_t code = uint32_t(q.a) | uint32_t(q.jx % 64) << 12 | uint32_t(q.jy % 64) << 18 |
+                        uint32_t(q.jx / 64) << 24 | uint32_t(q.jy / 64) << 26 | (1u << 30);
+        if (i == 0) code |= 1u << 31;
+        uint32_t wb;
+        std::memcpy(&wb, &q.w, 4);
+        table[2 * (s * 64 + l)] = code;
+        table[2 * (s * 64 + l) + 1] = wb;
+      }
+    }
+    for (; s < S; ++s) {
+      table[2 * (s * 64 + l)] = 1u << 31;   // invalid: zero weight, stores into the pad column
+      table[2 * (s * 64 + l) + 1] = 0u;
+    }
+  }
+  return int(S);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -353,13 +410,17 @@ int check_plan(epic_plan_t p, int array) {
   return EPIC_OK;
 }
 
-int check_grid_supported(const ArrayPlan& ap) {
+// small = the call needs the N <= 64 engine (stage-wise calls, adjoint).
+int check_grid_supported(const ArrayPlan& ap, bool small = false) {
   const HostArray& h = ap.h;
   if (h.nx != h.ny) return fail(EPIC_ERR_UNSUPPORTED, "only square grids are implemented (got %d x %d)", h.nx, h.ny);
+  if (small && h.nx > 64)
+    return fail(EPIC_ERR_UNSUPPORTED, "this call supports grids up to 64 x 64 (got %d); epic_run and epic_image "
+                "support 128 and 256", h.nx);
   if (!epic::image_supported(h.nx, h.na, ap.n_slots))
     return fail(EPIC_ERR_UNSUPPORTED,
-                "grid %d with %d antennas is not supported (N in {16,32,64}, Na <= 8N, <= 64 cells per lane)",
-                h.nx, h.na);
+                "grid %d with %d antennas is not supported (N in {16,32,64}: Na <= 8N; N in {128,256}: Na <= 512; "
+                "gridding schedule of %d slots per lane too long)", h.nx, h.na, ap.n_slots);
   return EPIC_OK;
 }
 
@@ -391,15 +452,19 @@ struct Timed {
   }
 };
 
-int pick_splits(epic_plan_t p, int F, int64_t T, int slots) {
+// Workgroups of one time split per channel (class groups of the N = 256 engine).
+int units_for(int N) { return N == 256 ? 4 : 1; }
+// Frames a workgroup images at once.
+int slots_for(int N) { return N >= 128 ? 1 : 4 * (64 / N); }
+
+int pick_splits(epic_plan_t p, int F, int64_t T, int N) {
   if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
   // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames per slot
-  int64_t s = (2048 + F - 1) / F;
-  s = std::min<int64_t>(s, std::max<int64_t>(1, T / (8 * int64_t(slots))));
+  const int64_t units = int64_t(F) * units_for(N);
+  int64_t s = (2048 + units - 1) / units;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, T / (8 * int64_t(slots_for(N)))));
   return int(std::max<int64_t>(1, s));
 }
-
-int slots_for(int N) { return 4 * (64 / N); }
 
 }  // namespace
 
@@ -480,6 +545,10 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       std::vector<uint32_t> tab;
       const int L = epic::grid_lanes(ap.h.nx);
       ap.n_slots = build_slots(ap.h, L, epic::grid_pitch(ap.h.nx), tab);
+      rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+    } else if (!rc && ap.h.nx == ap.h.ny && (ap.h.nx == 128 || ap.h.nx == 256)) {
+      std::vector<uint32_t> tab;
+      ap.n_slots = build_slots_cls(ap.h, tab);
       rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
     }
     if (rc) {
@@ -581,7 +650,7 @@ int epic_grid(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, i
   int rc = check_plan(plan, array);
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
-  if ((rc = check_grid_supported(ap))) return rc;
+  if ((rc = check_grid_supported(ap, true))) return rc;
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (nt > 0 && (!efield || !u || !grid)) return fail(EPIC_ERR_ARG, "efield, u and grid must not be NULL");
   epic::GridArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
@@ -595,7 +664,7 @@ int epic_image_accumulate(epic_plan_t plan, int32_t array, const float* grid, in
   int rc = check_plan(plan, array);
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
-  if ((rc = check_grid_supported(ap))) return rc;
+  if ((rc = check_grid_supported(ap, true))) return rc;
   if (nt < 0) return fail(EPIC_ERR_ARG, "nt must be >= 0");
   if (nt > 0 && (!grid || !image)) return fail(EPIC_ERR_ARG, "grid and image must not be NULL");
   if (tap && !ap.has_model) return fail(EPIC_ERR_STATE, "tap requested but no model (calibrator pixel) set");
@@ -659,7 +728,7 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
       return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
     const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
-    const int splits = pick_splits(plan, ap.h.F, n_samples, slots_for(ap.h.nx));
+    const int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx);
     const size_t uh = size_t(n_int) * ap.h.F * ap.h.na * sizeof(float2);
     const size_t pt = size_t(splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float);
     need = std::max(need, ((uh + 255) / 256) * 256 + pt);
@@ -673,7 +742,7 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     const HostArray& h = ap.h;
     const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
     if (n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
-    const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+    const int splits = pick_splits(plan, h.F, n_samples, h.nx);
     float2* uhist = static_cast<float2*>(scr);
     const size_t uh = size_t(n_int) * h.F * h.na * sizeof(float2);
     float* partial = reinterpret_cast<float*>(static_cast<char*>(scr) + ((uh + 255) / 256) * 256);
@@ -703,7 +772,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image must not be NULL");
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+  const int splits = pick_splits(plan, h.F, n_samples, h.nx);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
@@ -721,12 +790,12 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   int rc = check_plan(plan, array);
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
-  if ((rc = check_grid_supported(ap))) return rc;
+  if ((rc = check_grid_supported(ap, true))) return rc;
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   if (!efield || !gains || !dL_dI || !dL_dg) return fail(EPIC_ERR_ARG, "efield, gains, dL_dI and dL_dg must not be NULL");
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, slots_for(h.nx));
+  const int splits = pick_splits(plan, h.F, n_samples, h.nx);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);

@@ -103,6 +103,8 @@ struct AdjointArgs {
 // row pitch (complex values) that slot offsets refer to.
 int grid_lanes(int N);
 int grid_pitch(int N);
+// Slot rows available to the N = 128, 256 residue-class engine.
+int cls_table_slots();
 bool image_supported(int N, int na, int n_slots);
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);

@@ -153,6 +153,9 @@ def test_run_tiny_full(cuda):
     (64, synth.FMT_CI4, 2, 200, 301, 100),
     (16, synth.FMT_CF32, 2, 30, 64, 7),
     (64, synth.FMT_CI8, 1, 130, 40, 500),     # one interval shorter than t_cal
+    (128, synth.FMT_CI8, 2, 150, 120, 50),    # residue-class engine, 2 x 2 classes
+    (256, synth.FMT_CI4, 2, 300, 45, 20),     # residue-class engine, 4 x 4 classes
+    (128, synth.FMT_CF32, 1, 40, 30, 30),
 ])
 def test_run_small(cuda, n, efmt, kernel, na, n_samples, t_cal):
     wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_samples=n_samples, t_cal=t_cal)
@@ -202,9 +205,10 @@ def test_run_lwa_full_size_sampled_channels(cuda):
     assert np.all(np.isfinite(got["image"])) and np.all(got["status"] == 0)
 
 
-def test_fixed_gain_image(cuda):
+@pytest.mark.parametrize("n", [32, 128])
+def test_fixed_gain_image(cuda, n):
     torch = _torch()
-    wl = synth.config_small(n=32, n_chan=2, n_samples=77)
+    wl = synth.config_small(n=n, n_chan=2, n_samples=77)
     a = wl.array
     packed = synth.make_efield(wl)
     g = synth.random_gains(3, 2, a.n_ant)
@@ -216,6 +220,20 @@ def test_fixed_gain_image(cuda):
     for f in range(2):
         ref = O.image_fixed_gains(E[:, f], 1 / u32[f], cells, a.nx, a.ny, float(a.n_ant))
         assert image_err(img[f:f + 1], ref[None]).max() <= IMAGE_RTOL
+
+
+def test_run_hera_full_size_sampled_channels(cuda):
+    """The HERA-shaped workload at full size (350 antennas on a hexagonal
+    lattice, 8+8-bit, 512 channels, 128 x 128, 2000 samples, update every
+    100, off-centre calibrator); the oracle checks two channels."""
+    wl = synth.config_hera()
+    packed = synth.make_efield(wl, threads=16)
+    got = gpu_run(wl, packed, cuda)
+    chans = [3, 400]
+    ref = oracle_run(wl, packed[:, chans], channels=chans)
+    assert gain_err(got["hist"][:, chans], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"][chans], ref["image"]).max() <= IMAGE_RTOL
+    assert np.all(np.isfinite(got["image"]))
 
 
 def test_stagewise_equals_fused(cuda):
@@ -274,9 +292,14 @@ def test_single_sample_and_errors(cuda):
 
 def test_unsupported_grid_is_an_error(cuda):
     lib = _lib()
+    import torch
     wl = synth.config_small(n=32, n_ant=300)      # more than 8 antennas per lane
     with lib.Plan([wl.array]) as plan:
-        import torch
         with pytest.raises(lib.EpicError, match="UNSUPPORTED"):
             plan.grid(0, torch.from_numpy(synth.make_efield(wl)).to(cuda), 0, 1,
                       torch.ones((wl.array.n_chan, 300), dtype=torch.complex64, device=cuda))
+    wl = synth.config_small(n=128, n_ant=40, n_samples=4)   # stage-wise calls stop at 64 x 64
+    with lib.Plan([wl.array]) as plan:
+        with pytest.raises(lib.EpicError, match="UNSUPPORTED"):
+            plan.grid(0, torch.from_numpy(synth.make_efield(wl)).to(cuda), 0, 1,
+                      torch.ones((wl.array.n_chan, 40), dtype=torch.complex64, device=cuda))

@@ -207,7 +207,7 @@ void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) 
 //   antenna | LDS cell offset << 12 | first-of-cell << 31,  weight bits.
 // Padding slots store zero into the pad column (offset = grid size).
 // Returns the slot count S; table is [S][L] (lane fastest), 2 words each.
-int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table) {
+int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table, bool transposed = false) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
@@ -241,7 +241,7 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
     size_t s = 0;
     for (int c : lane_cells[l]) {
       const int cy = c / h.nx, cx = c % h.nx;
-      const uint32_t off = uint32_t(cy * pitch + cx);
+      const uint32_t off = transposed ? uint32_t(cx * pitch + cy) : uint32_t(cy * pitch + cx);
       const auto& lst = cell[c];
       for (size_t i = 0; i < lst.size(); ++i, ++s) {
         uint32_t code = uint32_t(lst[i].first) | (off << 12);
@@ -329,6 +329,8 @@ struct ArrayPlan {
   float* d_cell_w = nullptr;
   uint2* d_slots = nullptr;   // gridding schedule of the imaging engine
   int n_slots = 0;
+  uint2* d_slots_dft = nullptr;   // schedule of the DFT-GEMM engine (64 lanes, G^T)
+  int n_slots_dft = 0;
   uint8_t* d_flag = nullptr;
   bool has_model = false;
   double gamma = 0;
@@ -364,6 +366,7 @@ void free_array(ArrayPlan& p) {
   hipFree(p.d_cell_ixy);
   hipFree(p.d_cell_w);
   hipFree(p.d_slots);
+  hipFree(p.d_slots_dft);
   hipFree(p.d_flag);
   hipFree(p.d_k0);
   hipFree(p.d_A);
@@ -546,6 +549,10 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       const int L = epic::grid_lanes(ap.h.nx);
       ap.n_slots = build_slots(ap.h, L, epic::grid_pitch(ap.h.nx), tab);
       rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      if (!rc && (ap.h.nx == 32 || ap.h.nx == 64)) {
+        ap.n_slots_dft = build_slots(ap.h, 64, ap.h.nx + 2, tab, true);
+        rc = upload(&ap.d_slots_dft, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      }
     } else if (!rc && ap.h.nx == ap.h.ny && (ap.h.nx == 128 || ap.h.nx == 256)) {
       std::vector<uint32_t> tab;
       ap.n_slots = build_slots_cls(ap.h, tab);
@@ -695,11 +702,12 @@ static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64
                       int64_t t_cal, float* image, hipStream_t s, float* partial, int splits) {
   const HostArray& h = ap.h;
   const int N = h.nx;
+  const bool dft = plan->transform == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft);
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
-               ap.d_slots, ap.n_slots, splits, partial};
+               dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, splits, partial};
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s);
-    hipError_t e = epic::launch_image(N, ia, s);
+    hipError_t e = dft ? epic::launch_image_dft(N, ia, s) : epic::launch_image(N, ia, s);
     if (e != hipSuccess) return hip_fail(e, "imaging launch");
   }
   {

@@ -106,6 +106,10 @@ int grid_pitch(int N);
 // Slot rows available to the N = 128, 256 residue-class engine.
 int cls_table_slots();
 bool image_supported(int N, int na, int n_slots);
+// Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64; its gridding
+// schedule has 64 lanes and transposed (G^T) cell offsets.
+bool dft_supported(int N, int na, int n_slots);
+hipError_t launch_image_dft(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);
 hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);

@@ -30,7 +30,7 @@ def oracle_run(wl, packed, channels=None):
     return O.run(E, pb, wl.g0, channels=chans)
 
 
-def gpu_run(wl, packed, device, plan=None, splits=0, hist=True):
+def gpu_run(wl, packed, device, plan=None, splits=0, hist=True, transform=0):
     import torch
     from paper_1603_02126_amd import lib
     own = plan is None
@@ -39,6 +39,8 @@ def gpu_run(wl, packed, device, plan=None, splits=0, hist=True):
         plan.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
     if splits:
         plan.set_option(lib.OPT_SPLITS, splits)
+    if transform:
+        plan.set_option(lib.OPT_TRANSFORM, transform)
     a = wl.array
     e = torch.from_numpy(np.ascontiguousarray(packed)).to(device)
     g = torch.from_numpy(np.ascontiguousarray(wl.g0)).to(device)

@@ -23,7 +23,8 @@
 // transform of the gridded field evaluated at one pixel), so the feedback
 // recursion costs O(Na) per sample and the O(Ng log Ng) imaging of every
 // sample becomes independent work.
-#include "engine.h"
+#include "image_cls.h"
+#include "image_fft.h"
 
 namespace epic {
 
@@ -32,169 +33,24 @@ namespace epic {
 // ---------------------------------------------------------------------------
 template <int N, int APL>
 __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
-  using G = Geo<N>;
-  __shared__ float2 lds[G::LDS];
-  __shared__ float2 lds_e[G::SLOTS * APL * N];
-  __shared__ uint2 stab[Budget<N, APL>::TAB_SLOTS * N];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int h = lane / N, lam = lane % N;
-  const int slot = wave * G::FPW + h;
-  const int f = blockIdx.x % a.F;
-  const int s = blockIdx.x / a.F;
-  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
-  float2* buf = lds + slot * G::FRAME;
-  float2* epr = lds_e + slot * (APL * N);
-
-  load_slot_table(stab, a.slots, a.n_slots, N);
-  static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = make_float2(0.f, 0.f); });
-  __syncthreads();
-
-  float acc[N];
-  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
-
-  const int64_t iters = (te - tb + G::SLOTS - 1) / G::SLOTS;
-  Raw raw[APL];
-  float2 uu[APL];
-  {
-    const int64_t t = tb + slot;
-    fetch_frame<N, APL>(raw, uu, a.efield, a.u, t, a.t_cal, f, a.F, a.Na, a.fmt, lam, t < te);
-  }
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t t = tb + it * G::SLOTS + slot;
-    stage_frame<N, APL>(epr, raw, uu, lam, a.Na, a.fmt, t < te);
-    {
-      const int64_t tn = t + G::SLOTS;
-      fetch_frame<N, APL>(raw, uu, a.efield, a.u, tn, a.t_cal, f, a.F, a.Na, a.fmt, lam, tn < te);
-    }
-    wave_lds_sync();
-    grid_frame(buf, epr, stab, a.n_slots, N, lam);
-    wave_lds_sync();
-    float2 v[N];
-    transform_frame<N, +1>(buf, v, lam);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
-  }
-
-  // workgroup reduction of the SLOTS accumulators
-  __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);
-  static_for<0, N>([&](auto yc) {
-    constexpr int y = decltype(yc)::value;
-    red[(slot * N + y) * N + lam] = acc[y];
-  });
-  __syncthreads();
-  float* out = a.partial + (int64_t(s) * a.F + f) * (N * N);
-  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
-    float sum = 0.f;
-#pragma unroll
-    for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];
-    out[idx] = sum;
-  }
+  __shared__ __align__(16) uint8_t smem[FftSmem<N, APL>::BYTES];
+  image_item<N, APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
-
-// ---------------------------------------------------------------------------
-// Imaging of N = 64 R grids (R = 2, 4) by output residue classes.
-//
-// With k = R m + c and j = 64 p + q (m, q < 64; c, p < R) the transform
-// splits into R x R independent 64 x 64 transforms:
-//   X(R m + c) = sum_q exp(+2 pi i q.m / 64) H_c(q),
-//   H_c(q)    = sum_{j = q mod 64} G(j) exp(+2 pi i j.c / N)
-// so class c is the 64 x 64 engine applied to the grid folded modulo 64 with
-// the phase exp(+2 pi i j.c / N) on every contribution.  One wave owns one
-// class; the four waves of a workgroup image four classes of the same frame
-// from one shared E' staging area (one barrier per frame), and each class
-// writes its own interleaved subset of the partial image.
-// Slot code: antenna | qx << 12 | qy << 18 | px << 24 | py << 26 | valid << 30
-//            | first << 31.
-// ---------------------------------------------------------------------------
-constexpr int kClsMaxAnt = 512;
-constexpr int kClsTabSlots =
-    (kLdsBytes - 4 * Geo<64>::FRAME * 8 - 2 * kClsMaxAnt * 8 - 256 * 8) / (64 * 8);
 
 template <int R>
 __global__ __launch_bounds__(256) void k_image_cls(ImageArgs a) {
-  constexpr int N = 64 * R, CG = (R * R) / 4;
-  using G = Geo<64>;
-  constexpr int P = G::PITCH;
-  __shared__ float2 lds[4 * G::FRAME];
-  __shared__ float2 epr_l[2][kClsMaxAnt];
-  __shared__ float2 tw[N];
-  __shared__ uint2 stab[kClsTabSlots * 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = blockIdx.x % a.F;
+  __shared__ __align__(16) uint8_t smem[ClsSmem<R, false>::BYTES];
+  constexpr int CG = (R * R) / 4;
   const int rest = blockIdx.x / a.F;
-  const int cg = rest % CG, s = rest / CG;
-  const int c = cg * 4 + wave, cx = c % R, cy = c / R;
-  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
-  float2* buf = lds + wave * G::FRAME;
+  image_cls_item<R, false>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
+}
 
-  load_slot_table(stab, a.slots, a.n_slots, 64);
-  for (int k = tid; k < N; k += 256) {
-    double sn, cs;
-    sincospi(2.0 * double(k) / double(N), &sn, &cs);
-    tw[k] = make_float2(float(cs), float(sn));
-  }
-  static_for<0, 64>([&](auto xc) { buf[lane * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-  float acc[64];
-  static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
-
-  // antennas staged by this thread: tid and tid + 256
-  Raw raw[2];
-  float2 uu[2];
-  auto fetch = [&](int64_t t, bool active) {
-    const int bpe = a.fmt == kCF32 ? 8 : a.fmt == kCI8 ? 2 : 1;
-    const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
-    const float2* urow = a.u + ((t / a.t_cal) * a.F + f) * int64_t(a.Na);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int an = tid + 256 * i;
-      if (active && an < a.Na) {
-        raw[i] = load_raw(row, an, a.fmt);
-        uu[i] = urow[an];
-      } else {
-        raw[i] = Raw{0u, 0u};
-        uu[i] = make_float2(0.f, 0.f);
-      }
-    }
-  };
-  fetch(tb, tb < te);
-  __syncthreads();
-  for (int64_t t = tb; t < te; ++t) {
-    float2* epr = epr_l[(t - tb) & 1];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int an = tid + 256 * i;
-      if (an < a.Na) epr[an] = cmul(unpack_raw(raw[i], a.fmt), uu[i]);
-    }
-    fetch(t + 1, t + 1 < te);
-    __syncthreads();
-    // grid class (cx, cy): owned sub-cells, each contribution phased by exp(+2 pi i j.c / N)
-    float2 sum = make_float2(0.f, 0.f);
-#pragma unroll 4
-    for (int k = 0; k < a.n_slots; ++k) {
-      const uint2 e = stab[k * 64 + lane];
-      const uint32_t code = e.x;
-      const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
-      const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
-      const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
-      const float w = __uint_as_float(e.y);
-      const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
-      const bool first = int(code) < 0;
-      sum.x = first ? ev.x : sum.x + ev.x;
-      sum.y = first ? ev.y : sum.y + ev.y;
-      const int off = (code >> 30) & 1 ? qy * P + qx : 64;
-      buf[off] = sum;
-    }
-    wave_lds_sync();
-    float2 v[64];
-    transform_frame<64, +1>(buf, v, lane);
-    static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
-  }
-  // class pixels: (R ky + cy, R kx + cx) with kx = lane
-  float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
-  static_for<0, 64>([&](auto yc) {
-    constexpr int y = decltype(yc)::value;
-    out[(R * y + cy) * N + R * lane + cx] = acc[y];
-  });
+template <int R>
+__global__ __launch_bounds__(256) void k_image_cls_big(ImageArgs a) {
+  __shared__ __align__(16) uint8_t smem[ClsSmem<R, true>::BYTES];
+  constexpr int CG = (R * R) / 4;
+  const int rest = blockIdx.x / a.F;
+  image_cls_item<R, true>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,8 +164,14 @@ int grid_pitch(int N) { return N + 2; }
 
 int cls_table_slots() { return kClsTabSlots; }
 
+// 1: slot table in LDS, 2: dense-array variant, 0: unsupported
+int cls_variant(int na, int n_slots) {
+  if (na <= kClsMaxAnt && n_slots <= kClsTabSlots) return 1;
+  return na <= kClsMaxAntBig ? 2 : 0;
+}
+
 bool image_supported(int N, int na, int n_slots) {
-  if (N == 128 || N == 256) return na <= kClsMaxAnt && n_slots <= kClsTabSlots;
+  if (N == 128 || N == 256) return cls_variant(na, n_slots) != 0;
   if (!(N == 16 || N == 32 || N == 64) || na > 8 * N) return false;
   const int apl = apl_for(N, na);
   return apl != 0 && n_slots <= tab_slots_for(N, apl);
@@ -324,12 +186,13 @@ struct LaunchImage {
 };
 
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
-  if (N == 128) {
-    hipLaunchKernelGGL((k_image_cls<2>), dim3(a.F * 1 * a.splits), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-  if (N == 256) {
-    hipLaunchKernelGGL((k_image_cls<4>), dim3(a.F * 4 * a.splits), dim3(256), 0, s, a);
+  if (N == 128 || N == 256) {
+    const bool big = cls_variant(a.Na, a.n_slots) == 2;
+    const dim3 grid(a.F * (N == 256 ? 4 : 1) * a.splits);
+    if (N == 128 && !big) hipLaunchKernelGGL((k_image_cls<2>), grid, dim3(256), 0, s, a);
+    else if (N == 128) hipLaunchKernelGGL((k_image_cls_big<2>), grid, dim3(256), 0, s, a);
+    else if (!big) hipLaunchKernelGGL((k_image_cls<4>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_image_cls_big<4>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   return dispatch_n<LaunchImage>(N, a.Na, a, s);

@@ -156,6 +156,7 @@ def test_run_tiny_full(cuda):
     (128, synth.FMT_CI8, 2, 150, 120, 50),    # residue-class engine, 2 x 2 classes
     (256, synth.FMT_CI4, 2, 300, 45, 20),     # residue-class engine, 4 x 4 classes
     (128, synth.FMT_CF32, 1, 40, 30, 30),
+    (256, synth.FMT_CI8, 2, 700, 30, 15),     # dense-array variant (Na > 512, slot table in memory)
 ])
 def test_run_small(cuda, n, efmt, kernel, na, n_samples, t_cal):
     wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_samples=n_samples, t_cal=t_cal)

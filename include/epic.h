@@ -141,25 +141,52 @@ int epic_plan_destroy(epic_plan_t plan);
  * epic_run): computes k0, A and D on the host and uploads them. */
 int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* model);
 
-/* Tuning options (key, value).  Keys:
+/* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)
- *   EPIC_OPT_TRANSFORM   0 = auto, 1 = FFT (FP32), 2 = DFT-GEMM (split-precision MFMA)
- *   EPIC_OPT_TIMING      1 = record HIP events around each kernel (see below) */
+ *   EPIC_OPT_TRANSFORM   0 = FFT, 1 = FFT (FP32), 2 = DFT-GEMM (FP16 hi+lo split on
+ *                        the matrix cores, FP32 accumulation; grids 32 and 64)
+ *   EPIC_OPT_TIMING      1 = record HIP events around each kernel (see below)
+ *   EPIC_OPT_BATCH       0 = batched when the plan has several arrays, 1 = always
+ *                        batched, 2 = never.  Batched, epic_run makes one launch per
+ *                        stage for all arrays: one calibration solve, one
+ *                        persistent imaging kernel pulling (array, channel, class,
+ *                        time split) items from a work queue, one reduction.
+ *   EPIC_OPT_GRAPH       1 = epic_run captures its batched launches in a hipGraph
+ *                        on a plan-owned stream (ordered after and before the
+ *                        caller's stream by events) and replays it while the
+ *                        buffers and n_samples stay the same. */
 #define EPIC_OPT_SPLITS 1
 #define EPIC_OPT_TRANSFORM 2
 #define EPIC_OPT_TIMING 3
+#define EPIC_OPT_BATCH 4
+#define EPIC_OPT_GRAPH 5
 int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 
 /* Kernel timing, when EPIC_OPT_TIMING is on.  Events are recorded on the
  * stream each kernel is launched on.  Fills ms[k] with the total elapsed
  * milliseconds and launches[k] with the launch count of kernel kind k since
  * the last call, for k < n (kinds: 0 calibration solve, 1 imaging,
- * 2 image reduction, 3 adjoint); waits for the recorded events. */
+ * 2 image reduction, 3 adjoint, 4 a whole graph replay); waits for the
+ * recorded events. */
 #define EPIC_TIMER_SOLVE 0
 #define EPIC_TIMER_IMAGE 1
 #define EPIC_TIMER_REDUCE 2
 #define EPIC_TIMER_ADJOINT 3
-#define EPIC_TIMER_COUNT 4
+#define EPIC_TIMER_GRAPH 4
+#define EPIC_TIMER_COUNT 5
+
+/* Autotuner: for every array, time the imaging launch of the given E-field
+ * stream (n_samples samples) with each candidate transform (FFT; DFT-GEMM for
+ * grids 32 and 64) and time-split count, and keep the fastest for later runs.
+ * Synchronous (waits for the device); efield: one device pointer per array. */
+int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples,
+                       epic_stream_t stream);
+
+/* Tuning state per array: tuning[3 i + 0] = transform (1 FFT, 2 DFT-GEMM,
+ * 0 = plan default), [3 i + 1] = time splits (0 = auto), [3 i + 2] = measured
+ * imaging time in microseconds (get only).  Host arrays of 3 * n_arrays. */
+int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning);
+int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning);
 int epic_plan_get_timing(epic_plan_t plan, double* ms, int64_t* launches, int32_t n);
 
 /* ---------------------------------------------------------------------- */

@@ -332,6 +332,10 @@ struct ArrayPlan {
   uint2* d_slots_dft = nullptr;   // schedule of the DFT-GEMM engine (64 lanes, G^T)
   int n_slots_dft = 0;
   uint8_t* d_flag = nullptr;
+  // tuning (0 = plan default): transform 1 FFT / 2 DFT-GEMM, time splits
+  int tune_transform = 0;
+  int tune_splits = 0;
+  double tune_us = 0;
   bool has_model = false;
   double gamma = 0;
   int t_cal = 1;
@@ -346,18 +350,43 @@ struct TimerRec {
   hipEvent_t a, b;
 };
 
+struct GraphKey {
+  std::vector<const void*> ptrs;
+  int64_t n_samples = -1;
+  uint64_t generation = 0;
+  bool operator==(const GraphKey& o) const {
+    return ptrs == o.ptrs && n_samples == o.n_samples && generation == o.generation;
+  }
+};
+
 struct epic_plan_s {
   int device = 0;
+  int n_cu = 256;
   std::vector<ArrayPlan> arrays;
   // scratch
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  uint64_t generation = 1;   // bumped whenever device tables or scratch move
   // options
   int splits = 0;
   int transform = 0;
+  int batch = 0;             // 0 auto (batched when >1 array), 1 on, 2 off
+  bool graph = false;
   bool timing = false;
   std::vector<TimerRec> timers;
   std::vector<hipEvent_t> event_pool;
+  // batched work list
+  int4* d_items = nullptr;
+  size_t items_cap = 0;
+  int n_items = 0;
+  std::vector<int> items_key;
+  int* d_counter = nullptr;
+  // captured graph and the private stream it runs on
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph_g = nullptr;
+  hipGraphExec_t graph_x = nullptr;
+  GraphKey graph_key;
 };
 
 namespace {
@@ -398,6 +427,7 @@ int scratch(epic_plan_t p, size_t bytes, void** out) {
     hipError_t e = hipMalloc(&p->d_scratch, bytes);
     if (e != hipSuccess) return fail(EPIC_ERR_ALLOC, "scratch hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
     p->scratch_bytes = bytes;
+    p->generation++;
   }
   *out = p->d_scratch;
   return EPIC_OK;
@@ -432,8 +462,10 @@ struct Timed {
   int kind;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(epic_plan_t p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
-    if (!p->timing) return;
+  bool on;
+  Timed(epic_plan_t p_, int kind_, hipStream_t s_, bool enable = true)
+      : p(p_), kind(kind_), s(s_), on(enable && p_->timing) {
+    if (!on) return;
     a = take();
     b = take();
     if (a) hipEventRecord(a, s);
@@ -449,7 +481,7 @@ struct Timed {
     return e;
   }
   ~Timed() {
-    if (!p->timing || !a || !b) return;
+    if (!on || !a || !b) return;
     hipEventRecord(b, s);
     p->timers.push_back({kind, a, b});
   }
@@ -460,7 +492,8 @@ int units_for(int N) { return N == 256 ? 4 : 1; }
 // Frames a workgroup images at once.
 int slots_for(int N) { return N >= 128 ? 1 : 4 * (64 / N); }
 
-int pick_splits(epic_plan_t p, int F, int64_t T, int N) {
+int pick_splits(epic_plan_t p, int F, int64_t T, int N, int tuned = 0) {
+  if (tuned > 0) return int(std::max<int64_t>(1, std::min<int64_t>(tuned, std::max<int64_t>(1, T))));
   if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
   // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames per slot
   const int64_t units = int64_t(F) * units_for(N);
@@ -520,6 +553,7 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
   epic_plan_t p = new (std::nothrow) epic_plan_s;
   if (!p) return fail(EPIC_ERR_ALLOC, "host allocation failed");
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e, "hipGetDevice");
@@ -577,6 +611,13 @@ int epic_plan_destroy(epic_plan_t plan) {
     hipEventDestroy(t.b);
   }
   for (auto e : plan->event_pool) hipEventDestroy(e);
+  if (plan->graph_x) hipGraphExecDestroy(plan->graph_x);
+  if (plan->graph_g) hipGraphDestroy(plan->graph_g);
+  if (plan->ev_in) hipEventDestroy(plan->ev_in);
+  if (plan->ev_out) hipEventDestroy(plan->ev_out);
+  if (plan->gstream) hipStreamDestroy(plan->gstream);
+  hipFree(plan->d_items);
+  hipFree(plan->d_counter);
   delete plan;
   return EPIC_OK;
 }
@@ -606,6 +647,7 @@ int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* mod
   ap.gamma = model->gamma;
   ap.t_cal = model->t_cal;
   ap.has_model = true;
+  plan->generation++;
   return EPIC_OK;
 }
 
@@ -622,6 +664,13 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
       return EPIC_OK;
     case EPIC_OPT_TIMING:
       plan->timing = value != 0;
+      return EPIC_OK;
+    case EPIC_OPT_BATCH:
+      if (value < 0 || value > 2) return fail(EPIC_ERR_ARG, "batch must be 0 (auto), 1 (on) or 2 (off)");
+      plan->batch = int(value);
+      return EPIC_OK;
+    case EPIC_OPT_GRAPH:
+      plan->graph = value != 0;
       return EPIC_OK;
     default:
       return fail(EPIC_ERR_ARG, "unknown option key %d", key);
@@ -699,22 +748,185 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
 }
 
 static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64_t n_samples, const float2* u,
-                      int64_t t_cal, float* image, hipStream_t s, float* partial, int splits) {
+                      int64_t t_cal, float* image, hipStream_t s, float* partial, int splits, bool timed = true) {
   const HostArray& h = ap.h;
   const int N = h.nx;
-  const bool dft = plan->transform == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft);
+  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
+  const bool dft = tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft);
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
                dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, splits, partial};
   {
-    Timed tm(plan, EPIC_TIMER_IMAGE, s);
+    Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     hipError_t e = dft ? epic::launch_image_dft(N, ia, s) : epic::launch_image(N, ia, s);
     if (e != hipSuccess) return hip_fail(e, "imaging launch");
   }
   {
-    Timed tm(plan, EPIC_TIMER_REDUCE, s);
+    Timed tm(plan, EPIC_TIMER_REDUCE, s, timed);
     const double scale = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
     hipError_t e = epic::launch_reduce(partial, splits, int64_t(h.F) * N * N, scale, image, s);
     if (e != hipSuccess) return hip_fail(e, "image reduction launch");
+  }
+  return EPIC_OK;
+}
+
+// Per-array layout of one epic_run in the plan scratch.
+struct RunLayout {
+  int64_t n_int;
+  int splits;
+  size_t u_off, p_off;
+};
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+static int engine_of(epic_plan_t plan, const ArrayPlan& ap) {
+  const HostArray& h = ap.h;
+  const int N = h.nx;
+  if (N >= 128) {
+    const int v = epic::cls_variant(h.na, ap.n_slots);
+    return epic::engine_code(v == 2 ? epic::kEngClsBig : epic::kEngCls, N, N / 64);
+  }
+  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
+  const int apl = (h.na + 63) / 64 <= 2 ? 2 : (h.na + 63) / 64 <= 4 ? 4 : 8;
+  if (tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft)) return epic::engine_code(epic::kEngDft, N, apl);
+  const int aplf = (h.na + N - 1) / N <= 2 ? 2 : (h.na + N - 1) / N <= 4 ? 4 : 8;
+  return epic::engine_code(epic::kEngFft, N, aplf);
+}
+
+static int solve_ps(const HostArray& h) {
+  const int RB = h.na * epic::efmt_bytes(h.efmt);
+  return RB % 16 == 0 ? 16 : RB % 4 == 0 ? 4 : 1;
+}
+
+// Work items {array, channel, class group, split}, most expensive first.
+static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int64_t n_samples) {
+  std::vector<int> key{int(n_samples & 0x7fffffff), int(n_samples >> 31)};
+  for (size_t i = 0; i < lay.size(); ++i) key.push_back(lay[i].splits);
+  if (key == plan->items_key && plan->d_items) return EPIC_OK;
+  struct It {
+    int4 w;
+    double cost;
+  };
+  std::vector<It> items;
+  for (size_t i = 0; i < lay.size(); ++i) {
+    const HostArray& h = plan->arrays[i].h;
+    const int N = h.nx, cg = N == 256 ? 4 : 1;
+    const double per_frame = double(N) * N * std::log2(double(N) * N) / cg + 32.0 * h.na;
+    for (int s = 0; s < lay[i].splits; ++s) {
+      const int64_t tb = n_samples * s / lay[i].splits, te = n_samples * (s + 1) / lay[i].splits;
+      for (int f = 0; f < h.F; ++f)
+        for (int c = 0; c < cg; ++c) items.push_back({make_int4(int(i), f, c, s), per_frame * double(te - tb)});
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+  std::vector<int4> w(items.size());
+  for (size_t k = 0; k < items.size(); ++k) w[k] = items[k].w;
+  if (w.size() > plan->items_cap) {
+    hipFree(plan->d_items);
+    plan->d_items = nullptr;
+    plan->items_cap = 0;
+    if (hipMalloc(&plan->d_items, w.size() * sizeof(int4)) != hipSuccess)
+      return fail(EPIC_ERR_ALLOC, "work list allocation failed");
+    plan->items_cap = w.size();
+    plan->generation++;
+  }
+  hipError_t e = hipMemcpy(plan->d_items, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "work list upload");
+  plan->n_items = int(w.size());
+  plan->items_key = key;
+  return EPIC_OK;
+}
+
+// Enqueue the whole run on `s`; batched selects the one-launch-per-stage form.
+static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char* scr, const void* const* efield,
+                       int64_t n_samples, double* const* gains, float* const* image, double* const* gain_hist,
+                       uint32_t* const* ant_status, hipStream_t s, bool batched, bool timed) {
+  const int na_arr = int(plan->arrays.size());
+  std::vector<epic::SolveArgs> sa(na_arr);
+  for (int i = 0; i < na_arr; ++i) {
+    ArrayPlan& ap = plan->arrays[i];
+    const HostArray& h = ap.h;
+    sa[i] = epic::SolveArgs{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt, ap.t_cal,
+                            int(lay[i].n_int), ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma,
+                            reinterpret_cast<double2*>(gains[i]), reinterpret_cast<float2*>(scr + lay[i].u_off),
+                            gain_hist ? reinterpret_cast<double2*>(gain_hist[i]) : nullptr,
+                            ant_status ? ant_status[i] : nullptr};
+  }
+  if (!batched) {
+    for (int i = 0; i < na_arr; ++i) {
+      ArrayPlan& ap = plan->arrays[i];
+      {
+        Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
+        hipError_t e = epic::launch_solve(sa[i], s);
+        if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
+      }
+      int rc = image_pass(plan, ap, efield[i], n_samples, reinterpret_cast<float2*>(scr + lay[i].u_off), ap.t_cal,
+                          image[i], s, reinterpret_cast<float*>(scr + lay[i].p_off), lay[i].splits, timed);
+      if (rc) return rc;
+    }
+    return EPIC_OK;
+  }
+  // calibration: one launch when every array shares the solve variant
+  {
+    Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
+    bool same = true;
+    const int j0 = plan->arrays[0].h.na > 1024 ? 2 : 1, ps0 = solve_ps(plan->arrays[0].h);
+    for (int i = 1; i < na_arr; ++i)
+      same = same && (plan->arrays[i].h.na > 1024 ? 2 : 1) == j0 && solve_ps(plan->arrays[i].h) == ps0;
+    if (same) {
+      epic::BatchSolveArgs b{};
+      b.n_arrays = na_arr;
+      b.chan_off[0] = 0;
+      for (int i = 0; i < na_arr; ++i) {
+        b.arr[i] = sa[i];
+        b.chan_off[i + 1] = b.chan_off[i] + plan->arrays[i].h.F;
+      }
+      hipError_t e = epic::launch_solve_batch(b, j0, ps0, s);
+      if (e != hipSuccess) return hip_fail(e, "batched calibration solve launch");
+    } else {
+      for (int i = 0; i < na_arr; ++i) {
+        hipError_t e = epic::launch_solve(sa[i], s);
+        if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
+      }
+    }
+  }
+  // imaging: one persistent launch over every array's work items
+  {
+    epic::BatchImageArgs b{};
+    b.n_arrays = na_arr;
+    for (int i = 0; i < na_arr; ++i) {
+      ArrayPlan& ap = plan->arrays[i];
+      const HostArray& h = ap.h;
+      const int code = engine_of(plan, ap);
+      const bool dft = code / 100 == epic::kEngDft;
+      b.arr[i] = ImageArgs{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt,
+                           reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal,
+                           dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, lay[i].splits,
+                           reinterpret_cast<float*>(scr + lay[i].p_off)};
+      b.code[i] = code;
+    }
+    b.items = plan->d_items;
+    b.n_items = plan->n_items;
+    b.counter = plan->d_counter;
+    Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
+    hipError_t e = epic::launch_image_batch(b, plan->n_cu, s);
+    if (e != hipSuccess) return hip_fail(e, "batched imaging launch");
+  }
+  {
+    epic::BatchReduceArgs b{};
+    b.n_arrays = na_arr;
+    b.off[0] = 0;
+    for (int i = 0; i < na_arr; ++i) {
+      const HostArray& h = plan->arrays[i].h;
+      b.partial[i] = reinterpret_cast<const float*>(scr + lay[i].p_off);
+      b.image[i] = image[i];
+      b.splits[i] = lay[i].splits;
+      b.per_split[i] = int64_t(h.F) * h.nx * h.ny;
+      b.scale[i] = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
+      b.off[i + 1] = b.off[i] + b.per_split[i];
+    }
+    Timed tm(plan, EPIC_TIMER_REDUCE, s, timed);
+    hipError_t e = epic::launch_reduce_batch(b, s);
+    if (e != hipSuccess) return hip_fail(e, "batched reduction launch");
   }
   return EPIC_OK;
 }
@@ -725,7 +937,9 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image arrays must not be NULL");
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   const int na_arr = int(plan->arrays.size());
+  std::vector<RunLayout> lay(na_arr);
   size_t need = 0;
+  bool all_batchable = na_arr <= epic::kMaxBatch;
   for (int i = 0; i < na_arr; ++i) {
     int rc = check_plan(plan, i);
     if (rc) return rc;
@@ -735,39 +949,87 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     if (!epic::solve_supported(ap.h.na, ap.h.efmt))
       return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
-    const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
-    const int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx);
-    const size_t uh = size_t(n_int) * ap.h.F * ap.h.na * sizeof(float2);
-    const size_t pt = size_t(splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float);
-    need = std::max(need, ((uh + 255) / 256) * 256 + pt);
+    lay[i].n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
+    if (lay[i].n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
+    lay[i].splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
+    lay[i].u_off = need;
+    need += align256(size_t(lay[i].n_int) * ap.h.F * ap.h.na * sizeof(float2));
+    lay[i].p_off = need;
+    need += align256(size_t(lay[i].splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float));
+    all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
+  const bool batched = all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));
+  if (plan->graph && !batched)
+    return fail(EPIC_ERR_UNSUPPORTED, "graph replay needs the batched form (EPIC_OPT_BATCH and supported engines)");
   void* scr = nullptr;
   int rc = scratch(plan, need, &scr);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < na_arr; ++i) {
-    ArrayPlan& ap = plan->arrays[i];
-    const HostArray& h = ap.h;
-    const int64_t n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
-    if (n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
-    const int splits = pick_splits(plan, h.F, n_samples, h.nx);
-    float2* uhist = static_cast<float2*>(scr);
-    const size_t uh = size_t(n_int) * h.F * h.na * sizeof(float2);
-    float* partial = reinterpret_cast<float*>(static_cast<char*>(scr) + ((uh + 255) / 256) * 256);
-    epic::SolveArgs sa{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt, ap.t_cal,
-                       int(n_int), ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma,
-                       reinterpret_cast<double2*>(gains[i]), uhist,
-                       gain_hist ? reinterpret_cast<double2*>(gain_hist[i]) : nullptr,
-                       ant_status ? ant_status[i] : nullptr};
-    {
-      Timed tm(plan, EPIC_TIMER_SOLVE, s);
-      hipError_t e = epic::launch_solve(sa, s);
-      if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
+  if (batched) {
+    if (!plan->d_counter) {
+      if (hipMalloc(&plan->d_counter, 256) != hipSuccess) return fail(EPIC_ERR_ALLOC, "counter allocation failed");
+      plan->generation++;
     }
-    rc = image_pass(plan, ap, efield[i], n_samples, uhist, ap.t_cal, image[i], s, partial, splits);
-    if (rc) return rc;
+    if ((rc = build_items(plan, lay, n_samples))) return rc;
   }
-  return EPIC_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!plan->graph)
+    return enqueue_run(plan, lay, static_cast<char*>(scr), efield, n_samples, gains, image, gain_hist, ant_status, s,
+                       batched, true);
+
+  // hipGraph: capture once per (buffers, n_samples, plan memory generation), replay afterwards
+  if (!plan->gstream) {
+    hipError_t e = hipStreamCreateWithFlags(&plan->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "graph stream setup");
+  }
+  GraphKey key;
+  key.n_samples = n_samples;
+  key.generation = plan->generation;
+  for (int i = 0; i < na_arr; ++i) {
+    key.ptrs.push_back(efield[i]);
+    key.ptrs.push_back(gains[i]);
+    key.ptrs.push_back(image[i]);
+    key.ptrs.push_back(gain_hist ? gain_hist[i] : nullptr);
+    key.ptrs.push_back(ant_status ? ant_status[i] : nullptr);
+  }
+  if (!(plan->graph_x && key == plan->graph_key)) {
+    if (plan->graph_x) hipGraphExecDestroy(plan->graph_x);
+    if (plan->graph_g) hipGraphDestroy(plan->graph_g);
+    plan->graph_x = nullptr;
+    plan->graph_g = nullptr;
+    hipError_t e = hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    rc = enqueue_run(plan, lay, static_cast<char*>(scr), efield, n_samples, gains, image, gain_hist, ant_status,
+                     plan->gstream, true, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(plan->gstream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    plan->graph_g = g;
+    plan->graph_x = x;
+    plan->graph_key = key;
+  }
+  hipError_t e = hipEventRecord(plan->ev_in, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->gstream, plan->ev_in, 0);
+  if (e != hipSuccess) return hip_fail(e, "graph stream ordering");
+  {
+    Timed tm(plan, EPIC_TIMER_GRAPH, plan->gstream, true);
+    e = hipGraphLaunch(plan->graph_x, plan->gstream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  e = hipEventRecord(plan->ev_out, plan->gstream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->ev_out, 0);
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "graph stream ordering");
 }
 
 int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const double* gains,
@@ -780,7 +1042,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image must not be NULL");
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, h.nx);
+  const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
@@ -803,7 +1065,7 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   if (!efield || !gains || !dL_dI || !dL_dg) return fail(EPIC_ERR_ARG, "efield, gains, dL_dI and dL_dg must not be NULL");
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, h.nx);
+  const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);
@@ -824,6 +1086,107 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   e = epic::launch_adjoint_reduce(partial, splits, h.F, h.na, reinterpret_cast<const double2*>(gains), scale,
                                   reinterpret_cast<double2*>(dL_dg), s);
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "adjoint reduction launch");
+}
+
+int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples, epic_stream_t stream) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (!efield) return fail(EPIC_ERR_ARG, "efield array is NULL");
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < int(plan->arrays.size()); ++i) {
+    int rc = check_plan(plan, i);
+    if (rc) return rc;
+    ArrayPlan& ap = plan->arrays[i];
+    if ((rc = check_grid_supported(ap))) return rc;
+    if (!efield[i]) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
+    const HostArray& h = ap.h;
+    std::vector<int> trs{1};
+    if (epic::dft_supported(h.nx, h.na, ap.n_slots_dft)) trs.push_back(2);
+    const int base = pick_splits(plan, h.F, n_samples, h.nx, 0);
+    std::vector<int> sps;
+    for (int c : {base / 2, base, 2 * base, 4 * base}) {
+      const int v = int(std::max<int64_t>(1, std::min<int64_t>(c, n_samples)));
+      if (std::find(sps.begin(), sps.end(), v) == sps.end()) sps.push_back(v);
+    }
+    const int max_sp = *std::max_element(sps.begin(), sps.end());
+    const size_t ub = align256(size_t(h.F) * h.na * sizeof(float2));
+    const size_t ib = align256(size_t(h.F) * h.nx * h.ny * sizeof(float));
+    void* scr = nullptr;
+    if ((rc = scratch(plan, ub + ib + size_t(max_sp) * h.F * h.nx * h.ny * sizeof(float), &scr))) return rc;
+    char* base_p = static_cast<char*>(scr);
+    std::vector<float2> ones(size_t(h.F) * h.na, make_float2(1.f, 0.f));
+    hipError_t e = hipMemcpy(base_p, ones.data(), ones.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "autotune setup");
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(EPIC_ERR_HIP, "event");
+    int best_tr = 1, best_sp = base;
+    double best_us = 1e300;
+    const int keep_tr = ap.tune_transform, keep_sp = ap.tune_splits;
+    for (int tr : trs)
+      for (int sp : sps) {
+        ap.tune_transform = tr;
+        ap.tune_splits = sp;
+        auto once = [&]() {
+          return image_pass(plan, ap, efield[i], n_samples, reinterpret_cast<const float2*>(base_p),
+                            std::numeric_limits<int64_t>::max(), reinterpret_cast<float*>(base_p + ub), s,
+                            reinterpret_cast<float*>(base_p + ub + ib), sp, false);
+        };
+        if ((rc = once())) break;
+        hipEventRecord(a, s);
+        for (int r = 0; r < 2 && !rc; ++r) rc = once();
+        hipEventRecord(b, s);
+        if (rc) break;
+        e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) {
+          rc = hip_fail(e, "autotune timing");
+          break;
+        }
+        const double us = 1e3 * ms / 2.0;
+        if (us < best_us) {
+          best_us = us;
+          best_tr = tr;
+          best_sp = sp;
+        }
+      }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) {
+      ap.tune_transform = keep_tr;
+      ap.tune_splits = keep_sp;
+      return rc;
+    }
+    ap.tune_transform = best_tr;
+    ap.tune_splits = best_sp;
+    ap.tune_us = best_us;
+  }
+  plan->generation++;
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "autotune synchronise");
+}
+
+int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning) {
+  if (!plan || !tuning) return fail(EPIC_ERR_ARG, "plan and tuning must not be NULL");
+  for (size_t i = 0; i < plan->arrays.size(); ++i) {
+    tuning[3 * i] = plan->arrays[i].tune_transform;
+    tuning[3 * i + 1] = plan->arrays[i].tune_splits;
+    tuning[3 * i + 2] = int32_t(std::min(plan->arrays[i].tune_us, 2e9));
+  }
+  return EPIC_OK;
+}
+
+int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning) {
+  if (!plan || !tuning) return fail(EPIC_ERR_ARG, "plan and tuning must not be NULL");
+  for (size_t i = 0; i < plan->arrays.size(); ++i)
+    if (tuning[3 * i] < 0 || tuning[3 * i] > 2 || tuning[3 * i + 1] < 0)
+      return fail(EPIC_ERR_ARG, "bad tuning entry for array %zu", i);
+  for (size_t i = 0; i < plan->arrays.size(); ++i) {
+    plan->arrays[i].tune_transform = tuning[3 * i];
+    plan->arrays[i].tune_splits = tuning[3 * i + 1];
+  }
+  plan->generation++;
+  return EPIC_OK;
 }
 
 }  // extern "C"

@@ -98,6 +98,43 @@ struct AdjointArgs {
   double2* partial;         // [splits][F][Na]
 };
 
+// Batched execution over several arrays (one launch per stage).
+constexpr int kMaxBatch = 16;
+enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3 };
+// Engine code of an array: 100 * engine + (N / 32) * 10 + (APL or R).
+inline int engine_code(int engine, int N, int param) { return 100 * engine + (N / 32) * 10 + param; }
+
+struct BatchImageArgs {
+  ImageArgs arr[kMaxBatch];
+  int code[kMaxBatch];
+  int n_arrays;
+  const int4* items;        // {array, channel, class group, split}, largest first
+  int n_items;
+  int* counter;             // work-queue head (reset by the launcher)
+};
+
+struct BatchSolveArgs {
+  SolveArgs arr[kMaxBatch];
+  int chan_off[kMaxBatch + 1];   // prefix sums of channel counts
+  int n_arrays;
+};
+
+struct BatchReduceArgs {
+  const float* partial[kMaxBatch];
+  float* image[kMaxBatch];
+  int splits[kMaxBatch];
+  int64_t per_split[kMaxBatch];
+  double scale[kMaxBatch];
+  int64_t off[kMaxBatch + 1];
+  int n_arrays;
+};
+
+bool batch_engine_supported(int code);
+hipError_t launch_image_batch(const BatchImageArgs& b, int n_workgroups, hipStream_t s);
+hipError_t launch_solve_batch(const BatchSolveArgs& b, int j, int ps, hipStream_t s);
+hipError_t launch_reduce_batch(const BatchReduceArgs& b, hipStream_t s);
+int cls_variant(int na, int n_slots);
+
 // Launchers: return hipSuccess or the launch error.  N = grid size.
 // Gridding schedule geometry of the N <= 64 engine: lanes per frame and LDS
 // row pitch (complex values) that slot offsets refer to.

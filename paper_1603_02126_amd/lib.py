@@ -23,8 +23,8 @@ EPIC_OK, EPIC_ERR_ARG, EPIC_ERR_ALLOC, EPIC_ERR_HIP, EPIC_ERR_UNSUPPORTED, EPIC_
 _NAMES = {EPIC_ERR_ARG: "EPIC_ERR_ARG", EPIC_ERR_ALLOC: "EPIC_ERR_ALLOC", EPIC_ERR_HIP: "EPIC_ERR_HIP",
           EPIC_ERR_UNSUPPORTED: "EPIC_ERR_UNSUPPORTED", EPIC_ERR_STATE: "EPIC_ERR_STATE"}
 CF32, CI8, CI4 = 0, 1, 2
-OPT_SPLITS, OPT_TRANSFORM, OPT_TIMING = 1, 2, 3
-TIMER_SOLVE, TIMER_IMAGE, TIMER_REDUCE, TIMER_ADJOINT, TIMER_COUNT = 0, 1, 2, 3, 4
+OPT_SPLITS, OPT_TRANSFORM, OPT_TIMING, OPT_BATCH, OPT_GRAPH = 1, 2, 3, 4, 5
+TIMER_SOLVE, TIMER_IMAGE, TIMER_REDUCE, TIMER_ADJOINT, TIMER_GRAPH, TIMER_COUNT = 0, 1, 2, 3, 4, 5
 ANT_FLAGGED, ANT_D_ZERO, ANT_NONFINITE = 1, 2, 4
 
 
@@ -74,6 +74,9 @@ _SIGS = {
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_image_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "epic_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "epic_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "epic_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -255,6 +258,25 @@ class Plan:
         n = np.zeros(TIMER_COUNT, np.int64)
         _check(load().epic_plan_get_timing(self._h, ms.ctypes.data, n.ctypes.data, TIMER_COUNT))
         return {k: (float(ms[k]), int(n[k])) for k in range(TIMER_COUNT)}
+
+    def autotune(self, efields, n_samples, stream=None):
+        """Time the candidate transforms / splits per array on these inputs and keep the fastest."""
+        ptrs = [self._efield(i, efields[i], f"efield[{i}]")[0] for i in range(len(self.specs))]
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        _check(load().epic_plan_autotune(self._h, arr, int(n_samples), _stream(stream)))
+        return self.get_tuning()
+
+    def get_tuning(self):
+        """[(transform, splits, imaging microseconds)] per array."""
+        t = np.zeros(3 * len(self.specs), np.int32)
+        _check(load().epic_plan_get_tuning(self._h, t.ctypes.data))
+        return [tuple(int(v) for v in t[3 * i:3 * i + 3]) for i in range(len(self.specs))]
+
+    def set_tuning(self, tuning):
+        t = np.zeros(3 * len(self.specs), np.int32)
+        for i, (tr, sp, *_) in enumerate(tuning):
+            t[3 * i], t[3 * i + 1] = tr, sp
+        _check(load().epic_plan_set_tuning(self._h, t.ctypes.data))
 
     def _dims(self, i):
         s = self.specs[i]

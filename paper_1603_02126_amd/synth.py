@@ -456,3 +456,37 @@ def unit_gains(n_chan, n_ant):
 def random_gains(seed, n_chan, n_ant, amp_lo=0.8, amp_hi=1.2):
     """Seeded gain estimates for stage-wise tests (not drawn from any workload)."""
     return draw_gains(_rng(np.random.SeedSequence(seed)), n_chan, n_ant, amp_lo, amp_hi)
+
+
+def config_uneven(seed: int = 5, n_chan: int = 256, n_samples: int = 500,
+                  n_ants=(64, 128, 256, 512, 1024, 1024, 2048, 2048),
+                  grids=(32, 64, 64, 128, 128, 256, 256, 256)):
+    """Several arrays of uneven size observed together: antennas uniform in a
+    disk of diameter 0.8 N dx on an N x N grid (dx = half a wavelength at the
+    top of the band), 8+8-bit E-fields, channels across 50-100 MHz, three
+    calibrators (100, 50, 25) plus 50 power-law sources per array, gains every
+    100 samples.  Returns one Workload per array; the brightest calibrator is
+    the tapped pixel and all three are in the model."""
+    out = []
+    for i, (na, n) in enumerate(zip(n_ants, grids)):
+        s_lay, s_g, s_sky, _ = (_rng(k) for k in _streams(seed * 1000 + i))
+        dx = 1.5
+        radius = 0.4 * n * dx
+        ant = layout_uniform_disk(s_lay, na, radius)
+        freq = (50.0 + (np.arange(n_chan) + 0.5) * 50.0 / n_chan) * 1e6
+        x0 = _grid_for_disk(radius, n, dx, 0.25)
+        arr = ArraySpec(ant_xy=ant, freq_hz=freq, nx=n, ny=n, dx=dx, dy=dx, x0=x0, y0=x0,
+                        kernel=2, efmt=FMT_CI8)
+        cal = random_disk_lm(s_sky, 3, 0.3)
+        lm = random_disk_lm(s_sky, 50, 0.5)
+        S = powerlaw_flux(s_sky, 50, 1.0, 10.0)
+        src = np.concatenate([np.column_stack([cal, [100.0, 50.0, 25.0]]), np.column_stack([lm, S])])
+        g = draw_gains(s_g, n_chan, na)
+        sigma_r = float(src[:, 2].sum())
+        qs = _quant_scale(src[:, 2], sigma_r, g, 32.0)
+        model = src.copy()
+        model[:, 2] /= qs * qs
+        out.append(Workload(name=f"uneven{i}", seed=seed * 1000 + i, array=arr, src_lmS=src, model_lmS=model,
+                            cal_lm=cal[0].copy(), g_true=g, g0=np.ones((n_chan, na), np.complex128),
+                            gamma=0.5, t_cal=100, n_samples=n_samples, sigma_r=sigma_r, quant_scale=qs))
+    return out

@@ -6,7 +6,7 @@ from oracle import epic_oracle as O
 from paper_1603_02126_amd import synth
 
 IMAGE_RTOL = 1e-5   # max |I_gpu - I_oracle| / max |I_oracle| per channel
-GAIN_RTOL = 1e-4    # max_a |g_gpu - g_oracle| / |g_oracle|
+GAIN_RTOL = 1e-4    # max_a |g_gpu - g_oracle| / rms_a |g_oracle|, per channel (and interval)
 
 
 def image_err(gpu, ref):
@@ -19,7 +19,12 @@ def image_err(gpu, ref):
 
 
 def gain_err(gpu, ref):
-    return float(np.max(np.abs(gpu - ref) / np.abs(ref)))
+    """Normwise relative gain error: for every channel (and interval), the
+    largest antenna deviation divided by the rms gain magnitude."""
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2, axis=-1, keepdims=True))
+    return float(np.max(np.abs(gpu - ref) / rms))
 
 
 def oracle_run(wl, packed, channels=None):

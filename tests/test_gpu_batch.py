@@ -25,12 +25,12 @@ def _run(plan, wls, packs, dev, n_repeat=1):
     return outs
 
 
-def _plan(wls, **opts):
+def _plan(wls, opts=None):
     from paper_1603_02126_amd import lib
     plan = lib.Plan([w.array for w in wls])
     for i, w in enumerate(wls):
         plan.set_model(i, w.model_lmS, w.cal_lm, w.gamma, w.t_cal)
-    for k, v in opts.items():
+    for k, v in (opts or {}).items():
         plan.set_option(k, v)
     return plan
 
@@ -56,8 +56,8 @@ def test_batched_equals_per_array(cuda):
     from paper_1603_02126_amd import lib
     wls = _small_uneven(n_chan=2, n_samples=70)
     packs = [synth.make_efield(w) for w in wls]
-    a = _plan(wls, **{lib.OPT_BATCH: 1})
-    b = _plan(wls, **{lib.OPT_BATCH: 2})
+    a = _plan(wls, {lib.OPT_BATCH: 1})
+    b = _plan(wls, {lib.OPT_BATCH: 2})
     (ga, ia), = _run(a, wls, packs, cuda)
     (gb, ib), = _run(b, wls, packs, cuda)
     for k in range(len(wls)):
@@ -74,9 +74,9 @@ def test_graph_replays_match_eager(cuda):
     from paper_1603_02126_amd import lib
     wls = _small_uneven(n_chan=2, n_samples=50)
     packs = [synth.make_efield(w) for w in wls]
-    eager = _plan(wls, **{lib.OPT_BATCH: 1})
+    eager = _plan(wls, {lib.OPT_BATCH: 1})
     (ge, ie), = _run(eager, wls, packs, cuda)
-    graph = _plan(wls, **{lib.OPT_BATCH: 1, lib.OPT_GRAPH: 1})
+    graph = _plan(wls, {lib.OPT_BATCH: 1, lib.OPT_GRAPH: 1})
     es = [torch.from_numpy(p).to(cuda) for p in packs]
     gs = [torch.zeros((w.array.n_chan, w.array.n_ant), dtype=torch.complex128, device=cuda) for w in wls]
     imgs = [torch.zeros((w.array.n_chan, w.array.ny, w.array.nx), dtype=torch.float32, device=cuda) for w in wls]

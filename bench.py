@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the calibrated EPIC loop on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwa]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwa|hera|uneven|diff|tiny]
 
 A step is one pass of the whole hot path over one batch of synthetic input:
 EPICal calibration solve (tap, correlation, damped FP64 update every t_cal
@@ -12,10 +12,18 @@ with the 2x2 kernel, 10,000 samples, gains updated every 100 samples.  The
 E-field stream is resident in HBM before timing starts; each step restarts
 from the same initial gains.
 
-Prints one JSON line (value = frames/s, frame = one channel x one sample),
-with the roofline of the dominant kernel measured by HIP events on the
-stream it runs on, and the FP64 oracle timed on the host cores on a bounded
-sample of the same workload.
+Other workloads: "hera" (350 antennas on a hexagonal lattice, 8+8-bit, 512
+channels, 128x128, 2000 samples), "uneven" (eight arrays of 64..2048 antennas
+on 32^2..256^2 grids, 256 channels, 500 samples: one step images all of
+them), "diff" (fixed-gain image plus its hand-written adjoint, 64 channels,
+1000 samples: one step is forward + backward).
+
+Prints one JSON line (value = frames/s, frame = one channel x one sample of
+one array), with the roofline of the dominant kernel measured by HIP events on
+the stream it runs on, the FP64 oracle timed on the host cores on a bounded
+sample of the same workload, and the alternative forms (split-precision
+DFT-GEMM on the matrix cores; batched launches in a hipGraph after autotuning)
+timed on the same inputs, with their error against the oracle.
 """
 import argparse
 import json
@@ -77,6 +85,15 @@ def imaging_flops_per_frame(n, na, k2):
     return 5 * ng * math.log2(ng) + na * (6 + 4 * k2) + 4 * ng
 
 
+def adjoint_flops_per_frame(n, na, k2):
+    """Algorithmic flops of one frame of the adjoint: the forward frame again
+    (calibrate, grid, FFT), R * X (2 per pixel), the conjugate FFT, degridding
+    (4 per kernel cell per antenna) and the conj(E) product-accumulate (8 per
+    antenna)."""
+    ng = n * n
+    return 2 * 5 * ng * math.log2(ng) + na * (6 + 4 * k2) + 2 * ng + na * (4 * k2 + 8)
+
+
 def imaging_bytes_per_frame(na, bpe, n, n_samples, t_cal):
     """Algorithmic HBM bytes of one frame: the packed E-fields once, u once per
     interval per antenna, the image written once per run."""
@@ -86,10 +103,14 @@ def imaging_bytes_per_frame(na, bpe, n, n_samples, t_cal):
 def workload(name):
     if name == "lwa":
         return synth.config_lwa()
+    if name == "hera":
+        return synth.config_hera()
     if name == "tiny":
         return synth.config_tiny()
     if name == "diff":
         return synth.config_diff()
+    if name == "uneven":
+        return synth.config_uneven()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -102,46 +123,418 @@ def describe(wl):
             f"gains every {wl.t_cal} samples (gamma {wl.gamma})")
 
 
+def oracle_threads():
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        return int(max([d.get("num_threads", 1) for d in info] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def rel_err(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def gain_rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
+
+
 def cpu_baseline(wl, packed, budget_s, gpu_image=None, gpu_gains=None, extra_images=None):
     """The FP64 oracle on whole channels of the same workload until the time
     budget is spent (at least one channel)."""
     from oracle import epic_oracle as O
-    try:
-        import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        threads = max([d.get("num_threads", 1) for d in info] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
     pb = O.Problem.from_workload(wl)
-    E_all = packed
-    done, t_used = [], 0.0
-    results = []
-    ch = 0
+    done, results = [], []
+    ch, t_used = 0, 0.0
     t0 = time.perf_counter()
     while ch < wl.array.n_chan and (not done or t_used < budget_s):
-        E = O.unpack(E_all[:, ch], wl.array.efmt)
-        r = O.run_channel(E, pb, ch, wl.g0[ch])
-        results.append((ch, r))
+        E = O.unpack(packed[:, ch], wl.array.efmt)
+        results.append((ch, O.run_channel(E, pb, ch, wl.g0[ch])))
         done.append(ch)
         t_used = time.perf_counter() - t0
         ch += max(1, wl.array.n_chan // 7)
     frames = len(done) * wl.n_samples
-    out = {"value": frames / t_used, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
+    out = {"value": frames / t_used, "unit": "frames/s", "cores": oracle_threads(), "kind": "oracle",
            "sample": f"channels {done} x all {wl.n_samples} samples ({frames} frames, {t_used:.1f} s)"}
+    par = None
     if gpu_image is not None:
-        ie, ge = [], []
-        for c, r in results:
-            ref = r["image"]
-            ie.append(float(np.abs(gpu_image[c] - ref).max() / np.abs(ref).max()))
-            gr = r["gains"][-1]
-            ge.append(float(np.max(np.abs(gpu_gains[c] - gr)) / np.sqrt(np.mean(np.abs(gr) ** 2))))
-        out_par = {"channels": done, "image_rel_err": max(ie), "gain_rel_err": max(ge)}
+        par = {"channels": done,
+               "image_rel_err": max(rel_err(gpu_image[c], r["image"]) for c, r in results),
+               "gain_rel_err": max(gain_rel_err(gpu_gains[c], r["gains"][-1]) for c, r in results)}
         for name, im in (extra_images or {}).items():
-            out_par[f"{name}_image_rel_err"] = max(float(np.abs(im[c] - r["image"]).max() / np.abs(r["image"]).max())
-                                                   for c, r in results)
-    else:
-        out_par = None
-    return out, out_par
+            par[f"{name}_image_rel_err"] = max(rel_err(im[c], r["image"]) for c, r in results)
+    return out, par
+
+
+class Timer:
+    """Times K steps of `step` after W warm-up steps, with the library's HIP
+    event timers (recorded on the stream each kernel runs on) switched on for
+    the timed steps only."""
+
+    def __init__(self, plans):
+        self.plans = plans
+
+    def __call__(self, step, steps, warmup):
+        import torch
+        from paper_1603_02126_amd import lib
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        for p in self.plans:
+            p.set_option(lib.OPT_TIMING, 1)
+            p.timing()   # reset
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        kt = {}
+        for p in self.plans:
+            for k, (ms, n) in p.timing().items():
+                a, b = kt.get(k, (0.0, 0))
+                kt[k] = (a + ms, b + n)
+            p.set_option(lib.OPT_TIMING, 0)
+        return elapsed, kt
+
+
+def per_step(kt, kind, steps):
+    ms, n = kt.get(kind, (0.0, 0))
+    return {"ms_per_step": ms / steps, "launches_per_step": n / steps}
+
+
+def base_record(args, metric_value, ms_step, dtype, config):
+    return {
+        "metric": "EPIC frames/s (grid+FFT+|E|^2+EPICal) vs plain FP32 path; % HBM roofline",
+        "value": metric_value,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded generator: random layout, power-law sky, complex-Gaussian sources and noise, "
+                "quantised)",
+        "config": config,
+    }
+
+
+def copy_reference(dev):
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("# copy reference: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+
+
+def new_plan(specs_wls, opts=None):
+    from paper_1603_02126_amd import lib
+    plan = lib.Plan([w.array for w in specs_wls])
+    for i, w in enumerate(specs_wls):
+        plan.set_model(i, w.model_lmS, w.cal_lm, w.gamma, w.t_cal)
+    for k, v in (opts or {}).items():
+        plan.set_option(k, v)
+    return plan
+
+
+def bench_single(args, dev):
+    """One array through epic_run (lwa, hera, tiny)."""
+    import torch
+    from paper_1603_02126_amd import lib
+    wl = workload(args.workload)
+    a = wl.array
+    print(f"# generating {describe(wl)}", file=sys.stderr, flush=True)
+    tg = time.perf_counter()
+    packed = synth.make_efield(wl, threads=min(16, os.cpu_count() or 1))
+    print(f"# generated {packed.nbytes / 1e6:.1f} MB in {time.perf_counter() - tg:.1f} s", file=sys.stderr,
+          flush=True)
+
+    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None)
+    e = torch.from_numpy(packed).to(dev)
+    g0 = torch.from_numpy(wl.g0).to(dev)
+    g = torch.empty_like(g0)
+    img = torch.zeros((a.n_chan, a.ny, a.nx), dtype=torch.float32, device=dev)
+
+    def stepper(pl, out_img):
+        def step():
+            g.copy_(g0)
+            pl.run([e], wl.n_samples, [g], [out_img])
+        return step
+
+    dt, tim = Timer([plan])(stepper(plan, img), args.steps, args.warmup)
+    gains_plain = g.cpu().numpy()
+    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    frames = a.n_chan * wl.n_samples
+    forms = {}
+    if not args.no_forms:
+        if a.nx in (32, 64):
+            # form 1: split-precision DFT-GEMM on the matrix cores, same workload
+            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2})
+            img_d = torch.zeros_like(img)
+            dt_d, tim_d = Timer([plan_d])(stepper(plan_d, img_d), args.steps, args.warmup)
+            ms_img_d = tim_d[lib.TIMER_IMAGE][0] / max(1, tim_d[lib.TIMER_IMAGE][1])
+            mf = dft_mfma_flops_per_frame(a.nx) * frames / (ms_img_d * 1e-3) / 1e12
+            forms["dft_gemm_fp16_split"] = {
+                "ms_per_step": dt_d / args.steps * 1e3, "frames_per_s": frames / (dt_d / args.steps),
+                "speedup_vs_plain": dt / dt_d, "imaging_kernel_ms": ms_img_d,
+                "mfma": {"achieved": mf, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s (executed, fp16)",
+                         "frac": mf / PEAK_FP16_MFMA_TFLOPS},
+                "max_rel_diff_vs_plain": rel_err(img_d.cpu().numpy(), img.cpu().numpy()),
+                "_image": img_d}
+            plan_d.close()
+        else:
+            forms["dft_gemm_fp16_split"] = {"supported": False, "reason": "the DFT-GEMM form covers 32x32 and 64x64"}
+        # form 2: batched launches captured in a hipGraph, after autotuning
+        plan_g = new_plan([wl])
+        tuning = plan_g.autotune([e], wl.n_samples)
+        plan_g.set_option(lib.OPT_BATCH, 1)
+        plan_g.set_option(lib.OPT_GRAPH, 1)
+        img_g = torch.zeros_like(img)
+        dt_g, tim_g = Timer([plan_g])(stepper(plan_g, img_g), args.steps, args.warmup)
+        forms["batched_graph_autotuned"] = {
+            "ms_per_step": dt_g / args.steps * 1e3, "frames_per_s": frames / (dt_g / args.steps),
+            "speedup_vs_plain": dt / dt_g,
+            "tuning": {"transform": ["", "fft", "dft_gemm"][tuning[0][0]], "splits": tuning[0][1]},
+            "graph_replay_ms": tim_g[lib.TIMER_GRAPH][0] / max(1, tim_g[lib.TIMER_GRAPH][1]),
+            "max_rel_diff_vs_plain": rel_err(img_g.cpu().numpy(), img.cpu().numpy()),
+            "_image": img_g}
+        plan_g.close()
+    if args.copy_calib:
+        copy_reference(dev)
+
+    ms_step = dt / args.steps * 1e3
+    value = frames / (dt / args.steps)
+    k2 = 1 if a.kernel == 1 else 4
+    img_ms, img_n = tim[lib.TIMER_IMAGE]
+    avg_img_ms = img_ms / max(1, img_n)
+    flops_launch = imaging_flops_per_frame(a.nx, a.n_ant, k2) * frames
+    achieved = flops_launch / (avg_img_ms * 1e-3) / 1e12
+    bpe = synth.FMT_BYTES[a.efmt]
+    bytes_launch = imaging_bytes_per_frame(a.n_ant, bpe, a.nx, wl.n_samples, wl.t_cal) * frames
+    traffic = measured_traffic(args.workload) if not args.splits else None
+    kernels = {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+               "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps),
+               "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)}
+
+    cpu, parity = None, None
+    if args.cpu_budget > 0:
+        print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        extra = {k: v["_image"].cpu().numpy() for k, v in forms.items() if "_image" in v}
+        cpu, parity = cpu_baseline(wl, packed, args.cpu_budget, img.cpu().numpy(), gains_plain, extra)
+    for v in forms.values():
+        v.pop("_image", None)
+
+    engine = "k_image (calibrate+grid+FFT+|X|^2)" if a.nx <= 64 else \
+        f"k_image_cls<{a.nx // 64}> (calibrate+grid by residue class+64-point FFTs+|X|^2)"
+    out = base_record(args, value, ms_step, "f32", {
+        "workload": describe(wl), "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan,
+        "grid": [a.ny, a.nx], "n_samples": wl.n_samples, "t_cal": wl.t_cal, "efmt": synth.FMT_NAMES[a.efmt],
+        "path": "plain FP32 FFT", "parallelism": "1 GPU"})
+    out.update({
+        "msamples_per_s": value * a.n_ant / 1e6,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel": engine, "avg_launch_ms": avg_img_ms,
+                     "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
+                     "hbm_bytes_per_frame": bytes_launch / frames,
+                     "hbm_frac": bytes_launch / (avg_img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+        "forms": forms,
+    })
+    plan.close()
+    return out
+
+
+def bench_uneven(args, dev):
+    """Eight arrays of uneven size: per-array launches (plain) against the
+    batched persistent form in a hipGraph after autotuning."""
+    import torch
+    from paper_1603_02126_amd import lib
+    wls = workload("uneven")
+    print(f"# generating {len(wls)} arrays", file=sys.stderr, flush=True)
+    tg = time.perf_counter()
+    packs = [synth.make_efield(w, threads=min(16, os.cpu_count() or 1)) for w in wls]
+    print(f"# generated {sum(p.nbytes for p in packs) / 1e6:.1f} MB in {time.perf_counter() - tg:.1f} s",
+          file=sys.stderr, flush=True)
+    T = wls[0].n_samples
+    es = [torch.from_numpy(p).to(dev) for p in packs]
+    g0s = [torch.from_numpy(w.g0).to(dev) for w in wls]
+    gs = [torch.empty_like(g) for g in g0s]
+
+    def images():
+        return [torch.zeros((w.array.n_chan, w.array.ny, w.array.nx), dtype=torch.float32, device=dev) for w in wls]
+
+    def stepper(pl, imgs):
+        def step():
+            for g, g0 in zip(gs, g0s):
+                g.copy_(g0)
+            pl.run(es, T, gs, imgs)
+        return step
+
+    plan = new_plan(wls, {lib.OPT_BATCH: 2})
+    imgs = images()
+    dt, tim = Timer([plan])(stepper(plan, imgs), args.steps, args.warmup)
+    gains_plain = [g.cpu().numpy() for g in gs]
+    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    frames = sum(w.array.n_chan for w in wls) * T
+    flops_step = sum(imaging_flops_per_frame(w.array.nx, w.array.n_ant, 4) * w.array.n_chan * T for w in wls)
+    forms = {}
+    if not args.no_forms:
+        plan_g = new_plan(wls)
+        tuning = plan_g.autotune(es, T)
+        plan_g.set_option(lib.OPT_BATCH, 1)
+        plan_g.set_option(lib.OPT_GRAPH, 1)
+        imgs_g = images()
+        dt_g, tim_g = Timer([plan_g])(stepper(plan_g, imgs_g), args.steps, args.warmup)
+        forms["batched_graph_autotuned"] = {
+            "ms_per_step": dt_g / args.steps * 1e3, "frames_per_s": frames / (dt_g / args.steps),
+            "speedup_vs_plain": dt / dt_g,
+            "tuning": [{"grid": w.array.nx, "n_ant": w.array.n_ant,
+                        "transform": ["", "fft", "dft_gemm"][t[0]], "splits": t[1]} for w, t in zip(wls, tuning)],
+            "graph_replay_ms": tim_g[lib.TIMER_GRAPH][0] / max(1, tim_g[lib.TIMER_GRAPH][1]),
+            "max_rel_diff_vs_plain": max(rel_err(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(imgs_g, imgs)),
+            "_images": imgs_g}
+        plan_g.close()
+    if args.copy_calib:
+        copy_reference(dev)
+    img_ms = tim[lib.TIMER_IMAGE][0] / args.steps
+    achieved = flops_step / (img_ms * 1e-3) / 1e12
+    bytes_step = sum(imaging_bytes_per_frame(w.array.n_ant, synth.FMT_BYTES[w.array.efmt], w.array.nx, T, w.t_cal)
+                     * w.array.n_chan * T for w in wls)
+
+    cpu, parity = None, None
+    if args.cpu_budget > 0:
+        # the oracle on channel 0 of every array (the workload's own mix), more channels while budget lasts
+        from oracle import epic_oracle as O
+        print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        done = []
+        ie, ge, ieg = [], [], []
+        ch = 0
+        while ch < wls[0].array.n_chan and (not done or time.perf_counter() - t0 < args.cpu_budget):
+            for i, (w, p) in enumerate(zip(wls, packs)):
+                pb = O.Problem.from_workload(w)
+                r = O.run_channel(O.unpack(p[:, ch], w.array.efmt), pb, ch, w.g0[ch])
+                ie.append(rel_err(imgs[i][ch].cpu().numpy(), r["image"]))
+                ge.append(gain_rel_err(gains_plain[i][ch], r["gains"][-1]))
+                if "batched_graph_autotuned" in forms:
+                    ieg.append(rel_err(forms["batched_graph_autotuned"]["_images"][i][ch].cpu().numpy(), r["image"]))
+            done.append(ch)
+            ch += max(1, wls[0].array.n_chan // 5)
+        t_used = time.perf_counter() - t0
+        fr = len(done) * len(wls) * T
+        cpu = {"value": fr / t_used, "unit": "frames/s", "cores": oracle_threads(), "kind": "oracle",
+               "sample": f"channels {done} of each of the {len(wls)} arrays x all {T} samples "
+                         f"({fr} array-frames, {t_used:.1f} s)"}
+        parity = {"channels": done, "image_rel_err": max(ie), "gain_rel_err": max(ge)}
+        if ieg:
+            parity["batched_graph_autotuned_image_rel_err"] = max(ieg)
+    for v in forms.values():
+        v.pop("_images", None)
+
+    ms_step = dt / args.steps * 1e3
+    value = frames / (dt / args.steps)
+    out = base_record(args, value, ms_step, "f32", {
+        "workload": "uneven: 8 arrays, antennas " + ",".join(str(w.array.n_ant) for w in wls) + ", grids " +
+                    ",".join(f"{w.array.nx}^2" for w in wls) + f", ci8, {wls[0].array.n_chan} channels each, "
+                    f"{T} samples, gains every {wls[0].t_cal}",
+        "frames_per_step": frames, "path": "plain FP32 FFT, one launch per array per stage",
+        "parallelism": "1 GPU"})
+    out.update({
+        "msamples_per_s": sum(w.array.n_ant * w.array.n_chan for w in wls) * T / (dt / args.steps) / 1e6,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "imaging kernels of all arrays (FFT, residue-class engines)",
+                     "imaging_ms_per_step": img_ms,
+                     "algorithmic_bytes_per_step": bytes_step,
+                     "hbm_frac": bytes_step / (img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "kernels": {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+                    "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps),
+                    "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)},
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+        "forms": forms,
+    })
+    plan.close()
+    return out
+
+
+def bench_diff(args, dev):
+    """Differentiable form: fixed-gain image (forward) and its hand-written
+    adjoint (backward) for L = sum (I - M)^2."""
+    import torch
+    from paper_1603_02126_amd import lib
+    wl = workload("diff")
+    a = wl.array
+    print(f"# generating {describe(wl)}", file=sys.stderr, flush=True)
+    packed = synth.make_efield(wl, threads=min(16, os.cpu_count() or 1))
+    plan = new_plan([wl])
+    e = torch.from_numpy(packed).to(dev)
+    g = torch.from_numpy(wl.g0).to(dev)
+    M_np = np.random.default_rng(5).uniform(0, 1, size=(a.n_chan, a.ny, a.nx))
+    M = torch.from_numpy(M_np).to(dev)
+    img = torch.empty((a.n_chan, a.ny, a.nx), dtype=torch.float32, device=dev)
+    grad = torch.empty((a.n_chan, a.n_ant), dtype=torch.complex128, device=dev)
+    R = torch.empty_like(img)
+
+    def step():
+        plan.image(0, e, wl.n_samples, g, out=img)
+        R.copy_(2.0 * (img.double() - M))   # dL/dI of the loss, then the adjoint
+        plan.image_adjoint(0, e, wl.n_samples, g, R, out=grad)
+
+    dt, tim = Timer([plan])(step, args.steps, args.warmup)
+    frames = a.n_chan * wl.n_samples
+    k2 = 4
+    adj_ms = tim[lib.TIMER_ADJOINT][0] / max(1, tim[lib.TIMER_ADJOINT][1])
+    fwd_ms = tim[lib.TIMER_IMAGE][0] / max(1, tim[lib.TIMER_IMAGE][1])
+    achieved = adjoint_flops_per_frame(a.nx, a.n_ant, k2) * frames / (adj_ms * 1e-3) / 1e12
+    cpu, parity = None, None
+    if args.cpu_budget > 0:
+        from oracle import epic_oracle as O
+        print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        cells = O.grid_cells(a.ant_xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+        got = grad.cpu().numpy()
+        t0 = time.perf_counter()
+        done, errs = [], []
+        ch = 0
+        while ch < a.n_chan and (not done or time.perf_counter() - t0 < args.cpu_budget):
+            E = O.unpack(packed[:, ch], a.efmt)
+            I = O.image_fixed_gains(E, wl.g0[ch], cells, a.nx, a.ny, float(a.n_ant))
+            ref = O.image_gain_gradient(E, wl.g0[ch], cells, a.nx, a.ny, float(a.n_ant), 2 * (I - M_np[ch]))
+            errs.append(float(np.abs(got[ch] - ref).max() / np.abs(ref).max()))
+            done.append(ch)
+            ch += max(1, a.n_chan // 7)
+        t_used = time.perf_counter() - t0
+        fr = len(done) * wl.n_samples
+        cpu = {"value": fr / t_used, "unit": "frames/s", "cores": oracle_threads(), "kind": "oracle",
+               "sample": f"forward + gradient, channels {done} x all {wl.n_samples} samples ({fr} frames, "
+                         f"{t_used:.1f} s)"}
+        parity = {"channels": done, "gradient_rel_err": max(errs)}
+    out = base_record(args, frames / (dt / args.steps), dt / args.steps * 1e3, "f32", {
+        "workload": describe(wl) + "; loss sum (I - M)^2, M seeded uniform [0, 1)",
+        "frames_per_step": frames, "path": "epic_image + epic_image_adjoint (forward + backward)",
+        "parallelism": "1 GPU"})
+    out.update({
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "k_adjoint (recompute X, R*X, conjugate FFT, degrid, conj(E) product)",
+                     "avg_launch_ms": adj_ms,
+                     "flops_per_frame": adjoint_flops_per_frame(a.nx, a.n_ant, k2)},
+        "kernels": {"forward_imaging": {"ms_per_launch": fwd_ms}, "adjoint": {"ms_per_launch": adj_ms}},
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    })
+    plan.close()
+    return out
 
 
 def main():
@@ -149,7 +542,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lwa")
+    ap.add_argument("--workload", default="lwa", choices=["lwa", "hera", "tiny", "uneven", "diff"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
@@ -163,149 +556,15 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1603_02126_amd import lib
-
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    wl = workload(args.workload)
-    a = wl.array
-    print(f"# generating {describe(wl)}", file=sys.stderr, flush=True)
-    tg = time.perf_counter()
-    packed = synth.make_efield(wl, threads=min(16, os.cpu_count() or 1))
-    print(f"# generated {packed.nbytes / 1e6:.1f} MB in {time.perf_counter() - tg:.1f} s", file=sys.stderr,
-          flush=True)
-
-    plan = lib.Plan([a])
-    plan.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
-    if args.splits:
-        plan.set_option(lib.OPT_SPLITS, args.splits)
-    e = torch.from_numpy(packed).to(dev)
-    g0 = torch.from_numpy(wl.g0).to(dev)
-    g = torch.empty_like(g0)
-    img = torch.zeros((a.n_chan, a.ny, a.nx), dtype=torch.float32, device=dev)
-
-    def timed_steps(pl, out_img, steps, warmup):
-        def step():
-            g.copy_(g0)
-            pl.run([e], wl.n_samples, [g], [out_img])
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        pl.set_option(lib.OPT_TIMING, 1)
-        pl.timing()   # reset
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        kt = pl.timing()
-        pl.set_option(lib.OPT_TIMING, 0)
-        return elapsed, kt
-
-    dt, tim = timed_steps(plan, img, args.steps, args.warmup)
-    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
-    forms = {}
-    if not args.no_forms and a.nx in (32, 64):
-        # form 1: split-precision DFT-GEMM on the matrix cores, same workload
-        plan_d = lib.Plan([a])
-        plan_d.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
-        plan_d.set_option(lib.OPT_TRANSFORM, 2)
-        img_d = torch.zeros_like(img)
-        dt_d, tim_d = timed_steps(plan_d, img_d, args.steps, args.warmup)
-        ms_img_d = tim_d[lib.TIMER_IMAGE][0] / max(1, tim_d[lib.TIMER_IMAGE][1])
-        mf = dft_mfma_flops_per_frame(a.nx) * a.n_chan * wl.n_samples / (ms_img_d * 1e-3) / 1e12
-        forms["dft_gemm_fp16_split"] = {
-            "ms_per_step": dt_d / args.steps * 1e3, "frames_per_s": a.n_chan * wl.n_samples / (dt_d / args.steps),
-            "speedup_vs_plain": dt / dt_d, "imaging_kernel_ms": ms_img_d,
-            "mfma": {"achieved": mf, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s (executed, fp16)",
-                     "frac": mf / PEAK_FP16_MFMA_TFLOPS},
-            "_image": img_d}
-        plan_d.close()
-    if not args.no_forms:
-        # form 2: batched launches captured in a hipGraph, after autotuning
-        plan_g = lib.Plan([a])
-        plan_g.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
-        tuning = plan_g.autotune([e], wl.n_samples)
-        plan_g.set_option(lib.OPT_BATCH, 1)
-        plan_g.set_option(lib.OPT_GRAPH, 1)
-        img_g = torch.zeros_like(img)
-        dt_g, tim_g = timed_steps(plan_g, img_g, args.steps, args.warmup)
-        forms["batched_graph_autotuned"] = {
-            "ms_per_step": dt_g / args.steps * 1e3, "frames_per_s": a.n_chan * wl.n_samples / (dt_g / args.steps),
-            "speedup_vs_plain": dt / dt_g, "tuning": {"transform": ["", "fft", "dft_gemm"][tuning[0][0]],
-                                                      "splits": tuning[0][1]},
-            "graph_replay_ms": tim_g[lib.TIMER_GRAPH][0] / max(1, tim_g[lib.TIMER_GRAPH][1]),
-            "_image": img_g}
-        plan_g.close()
-    if args.copy_calib:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print("# copy reference: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
-        del src, dst
-
-    frames = a.n_chan * wl.n_samples
-    ms_step = dt / args.steps * 1e3
-    value = frames / (dt / args.steps)
-    k2 = 1 if a.kernel == 1 else 4
-    img_ms, img_n = tim[lib.TIMER_IMAGE]
-    avg_img_ms = img_ms / max(1, img_n)
-    flops_launch = imaging_flops_per_frame(a.nx, a.n_ant, k2) * frames
-    achieved = flops_launch / (avg_img_ms * 1e-3) / 1e12
-    bpe = synth.FMT_BYTES[a.efmt]
-    bytes_launch = imaging_bytes_per_frame(a.n_ant, bpe, a.nx, wl.n_samples, wl.t_cal) * frames
-    traffic = measured_traffic(args.workload) if not args.splits else None
-    kernels = {
-        "imaging": {"avg_ms": avg_img_ms, "launches": img_n},
-        "calibration_solve": {"avg_ms": tim[lib.TIMER_SOLVE][0] / max(1, tim[lib.TIMER_SOLVE][1]),
-                              "launches": tim[lib.TIMER_SOLVE][1]},
-        "image_reduce": {"avg_ms": tim[lib.TIMER_REDUCE][0] / max(1, tim[lib.TIMER_REDUCE][1]),
-                         "launches": tim[lib.TIMER_REDUCE][1]},
-    }
-
-    cpu, parity = None, None
-    if args.cpu_budget > 0:
-        print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        extra = {k: v["_image"].cpu().numpy() for k, v in forms.items()}
-        cpu, parity = cpu_baseline(wl, packed, args.cpu_budget, img.cpu().numpy(), g.cpu().numpy(), extra)
-    for v in forms.values():
-        v.pop("_image", None)
-
-    out = {
-        "metric": "EPIC frames/s (grid+FFT+|E|^2+EPICal) vs plain FP32 path; % HBM roofline",
-        "value": value,
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded generator: random layout, power-law sky, complex-Gaussian sources and noise, "
-                "quantised)",
-        "config": {"workload": describe(wl), "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan,
-                   "grid": [a.ny, a.nx], "n_samples": wl.n_samples, "t_cal": wl.t_cal,
-                   "efmt": synth.FMT_NAMES[a.efmt], "path": "plain FP32 FFT", "parallelism": "1 GPU"},
-        "msamples_per_s": value * a.n_ant / 1e6,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": bytes_launch,
-                     "kernel": "k_image (calibrate+grid+FFT+|X|^2)",
-                     "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
-                     "hbm_bytes_per_frame": bytes_launch / frames,
-                     "hbm_frac": bytes_launch / (avg_img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
-        "kernels": kernels,
-        "cpu_baseline": cpu,
-        "parity_vs_oracle": parity,
-        "forms": forms,
-    }
+    if args.workload == "uneven":
+        out = bench_uneven(args, dev)
+    elif args.workload == "diff":
+        out = bench_diff(args, dev)
+    else:
+        out = bench_single(args, dev)
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

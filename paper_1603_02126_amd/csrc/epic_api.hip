@@ -207,7 +207,9 @@ void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) 
 //   antenna | LDS cell offset << 12 | first-of-cell << 31,  weight bits.
 // Padding slots store zero into the pad column (offset = grid size).
 // Returns the slot count S; table is [S][L] (lane fastest), 2 words each.
-int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table, bool transposed = false) {
+// Rows y0 <= y < y1 only (re-based so that row y0 is row 0) when y1 > y0.
+int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table, bool transposed = false,
+                int y0 = 0, int y1 = 0) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
@@ -217,7 +219,8 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
     for (int k = 0; k < h.k2; ++k) {
       const size_t q = size_t(a) * h.k2 + k;
       if (w[q] == 0.0) continue;
-      cell[size_t(iy[q]) * h.nx + ix[q]].push_back({a, float(w[q])});
+      if (y1 > y0 && (iy[q] < y0 || iy[q] >= y1)) continue;
+      cell[size_t(iy[q] - (y1 > y0 ? y0 : 0)) * h.nx + ix[q]].push_back({a, float(w[q])});
     }
   }
   std::vector<int> order;
@@ -331,6 +334,8 @@ struct ArrayPlan {
   int n_slots = 0;
   uint2* d_slots_dft = nullptr;   // schedule of the DFT-GEMM engine (64 lanes, G^T)
   int n_slots_dft = 0;
+  uint2* d_slots_h = nullptr;     // 64 x 64: half-frame schedule (two halves of rows)
+  int n_slots_h0 = 0, n_slots_h1 = 0;
   uint8_t* d_flag = nullptr;
   // tuning (0 = plan default): transform 1 FFT / 2 DFT-GEMM, time splits
   int tune_transform = 0;
@@ -396,6 +401,7 @@ void free_array(ArrayPlan& p) {
   hipFree(p.d_cell_w);
   hipFree(p.d_slots);
   hipFree(p.d_slots_dft);
+  hipFree(p.d_slots_h);
   hipFree(p.d_flag);
   hipFree(p.d_k0);
   hipFree(p.d_A);
@@ -587,6 +593,13 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
         ap.n_slots_dft = build_slots(ap.h, 64, ap.h.nx + 2, tab, true);
         rc = upload(&ap.d_slots_dft, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }
+      if (!rc && ap.h.nx == 64) {
+        std::vector<uint32_t> hi;
+        ap.n_slots_h0 = build_slots(ap.h, 64, epic::grid_pitch(64), tab, false, 0, 32);
+        ap.n_slots_h1 = build_slots(ap.h, 64, epic::grid_pitch(64), hi, false, 32, 64);
+        tab.insert(tab.end(), hi.begin(), hi.end());
+        rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      }
     } else if (!rc && ap.h.nx == ap.h.ny && (ap.h.nx == 128 || ap.h.nx == 256)) {
       std::vector<uint32_t> tab;
       ap.n_slots = build_slots_cls(ap.h, tab);
@@ -754,7 +767,8 @@ static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64
   const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
   const bool dft = tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft);
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
-               dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, splits, partial};
+               dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, splits, partial,
+               ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     hipError_t e = dft ? epic::launch_image_dft(N, ia, s) : epic::launch_image(N, ia, s);

@@ -26,6 +26,10 @@ struct ImageArgs {
   int n_slots;
   int splits;               // workgroups per channel
   float* partial;           // [splits][F][N*N]
+  // 64 x 64 only: schedule of the half-frame gridding (rows 0..31, then rows
+  // 32..63, each re-based to row 0, 64 lanes); null when not built
+  const uint2* slots_h = nullptr;
+  int n_slots_h0 = 0, n_slots_h1 = 0;
 };
 
 // Stage-wise gridding to HBM.
@@ -143,6 +147,7 @@ int grid_pitch(int N);
 // Slot rows available to the N = 128, 256 residue-class engine.
 int cls_table_slots();
 bool image_supported(int N, int na, int n_slots);
+bool pair_engine(const ImageArgs& a, int N);   // the 64 x 64 two-waves-per-SIMD engine applies
 // Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64; its gridding
 // schedule has 64 lanes and transposed (G^T) cell offsets.
 bool dft_supported(int N, int na, int n_slots);

@@ -2,6 +2,7 @@
 // and the batched persistent kernel.
 #pragma once
 #include "engine.h"
+#include "xpose.h"
 
 namespace epic {
 
@@ -69,6 +70,124 @@ __device__ __forceinline__ void image_item(const ImageArgs& a, int f, int s, uin
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];
+    out[idx] = sum;
+  }
+  __syncthreads();
+}
+
+}  // namespace epic
+
+namespace epic {
+
+// ---------------------------------------------------------------------------
+// 64 x 64 engine with two waves per SIMD ("paired" engine).
+//
+// A wave64 issues a VALU instruction at most every other cycle of its SIMD's
+// FP32 pipeline, so the pipeline only runs at full rate with two waves
+// computing at the same time.  The one-wave engine above needs a 33 KB frame
+// buffer per wave, which leaves room for one wave per SIMD; here each of the
+// eight waves of a workgroup (two per SIMD) images its own frames with 19 KB:
+//   * gridding goes through half a frame (32 rows): the rows 0..31 are
+//     gridded and loaded by lanes 0..31, then the rows 32..63 by lanes
+//     32..63 (two schedules, built on the host), each lane zeroing the row it
+//     loaded;
+//   * after the row FFTs the frame is transposed in registers (xpose.h),
+//     with the same half buffer as staging for the low index bits;
+//   * column FFTs and |X|^2 accumulation as in the one-wave engine.
+// Waves never wait for each other inside the frame loop.  Integer E-field
+// formats (ci4, ci8) with 129..256 antennas (four per lane).
+// ---------------------------------------------------------------------------
+constexpr int kPairThreads = 512;
+
+template <int APL>
+struct PairSmem {
+  static constexpr int HALF = 32 * Geo<64>::PITCH;        // float2: half frame
+  static constexpr int WAVE = HALF + APL * 64;            // float2 per wave: half frame + E' staging
+  static constexpr int T_OFF = 8 * WAVE * 8;              // bytes: slot table
+  static constexpr int TAB_SLOTS = (kLdsBytes - T_OFF) / (64 * 8);
+  static constexpr int BYTES = T_OFF + TAB_SLOTS * 64 * 8;
+  static_assert(HALF >= kXposeFloat2, "the transpose staging reuses the half frame");
+  static_assert(8 * 64 * 64 * 4 <= T_OFF, "the accumulator reduction reuses the wave areas");
+};
+
+template <int APL>
+__device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  constexpr int N = 64, P = Geo<64>::PITCH, INFLIGHT = 8;
+  using L = PairSmem<APL>;
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float2* H = lds + wave * L::WAVE;
+  float2* epr = H + L::HALF;
+  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
+  const int S0 = a.n_slots_h0, S1 = a.n_slots_h1;
+  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
+
+  load_slot_table(stab, a.slots_h, S0 + S1, N);
+  if (lam < 32) static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  __syncthreads();
+
+  float acc[N];
+  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  float2 v[N];
+  uint32_t raw[APL];   // integer formats only: one packed sample per register
+  const int64_t iters = (te - tb + INFLIGHT - 1) / INFLIGHT;
+  const int bpe = efmt_bytes(a.fmt);
+  // the packed samples of a frame are prefetched one frame ahead; u (constant
+  // over an interval, cache resident) is loaded when the frame is staged
+  auto fetch_raw = [&](int64_t t) {
+    const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, a.fmt).x : 0u;
+    });
+  };
+  fetch_raw(tb + wave);
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t t = tb + it * INFLIGHT + wave;
+    const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      if (an < a.Na) epr[an] = t < te ? cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, a.fmt), urow[an])
+                                      : make_float2(0.f, 0.f);
+    });
+    fetch_raw(t + INFLIGHT);
+    wave_lds_sync();
+    // rows 0..31: grid, lanes 0..31 load their row and zero it
+    grid_frame(H, epr, stab, S0, N, lam);
+    wave_lds_sync();
+    if (lam < 32) {
+      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
+      static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    wave_lds_sync();
+    // rows 32..63
+    grid_frame(H, epr, stab + S0 * N, S1, N, lam);
+    wave_lds_sync();
+    if (lam >= 32) {
+      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
+      static_for<0, N>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    wave_lds_sync();
+    fft_reg<N, +1>(v);            // along x: lane = row y
+    transpose64(v, H, lam);       // lane = column kx
+    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    fft_reg<N, +1>(v);            // along y
+    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+  }
+
+  // workgroup reduction of the eight accumulators
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+  static_for<0, N>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    red[(wave * N + y) * N + lam] = acc[y];
+  });
+  __syncthreads();
+  float* out = a.partial + (int64_t(s) * a.F + f) * (N * N);
+  for (int idx = threadIdx.x; idx < N * N; idx += kPairThreads) {
+    float sum = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += red[q * N * N + idx];
     out[idx] = sum;
   }
   __syncthreads();

@@ -4,8 +4,9 @@
 // 64 / N frames of an N x N grid (N <= 64); lane lam of a frame owns grid row
 // lam.  Per frame:
 //   1. calibrate + grid (Sec. 2.1, E'_a = E_a / g_a and eq. gridding): each
-//      lane takes antennas lam, lam + N, ... and scatters w * u * E with LDS
-//      float atomics into the frame's zeroed LDS buffer;
+//      lane stages antennas lam, lam + N, ... as E' in LDS, then sums the
+//      contributions of the grid cells it owns (a fixed schedule built on the
+//      host) and stores them into the frame's LDS buffer;
 //   2. lane lam loads row lam into registers and runs an N-point FFT there;
 //   3. the row spectrum is written transposed to LDS (lane-consecutive
 //      addresses, conflict free) and lane lam reads back column lam (rows of
@@ -35,6 +36,13 @@ template <int N, int APL>
 __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   __shared__ __align__(16) uint8_t smem[FftSmem<N, APL>::BYTES];
   image_item<N, APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
+}
+
+template <int APL>
+__global__ __launch_bounds__(kPairThreads) void k_image_pair(ImageArgs a) {
+  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
+  image_item_pair<APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
 template <int R>
@@ -177,9 +185,23 @@ bool image_supported(int N, int na, int n_slots) {
   return apl != 0 && n_slots <= tab_slots_for(N, apl);
 }
 
+// The paired 64 x 64 engine: integer E-fields, 129..256 antennas (four per
+// lane: the register budget of two waves per SIMD is checked there), and a
+// half-frame schedule that fits its LDS table.
+bool pair_engine(const ImageArgs& a, int N) {
+  return N == 64 && a.fmt != kCF32 && apl_for(N, a.Na) == 4 && a.slots_h != nullptr &&
+         a.n_slots_h0 + a.n_slots_h1 <= PairSmem<4>::TAB_SLOTS;
+}
+
 template <int N, int APL>
 struct LaunchImage {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
+    if constexpr (N == 64 && APL == 4) {
+      if (pair_engine(a, N)) {
+        hipLaunchKernelGGL((k_image_pair<APL>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_image<N, APL>), dim3(a.F * a.splits), dim3(256), 0, s, a);
     return hipGetLastError();
   }

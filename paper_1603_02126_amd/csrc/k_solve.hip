@@ -54,9 +54,14 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <int MAXP>
+static int stage_cap(int RB) {
+  return RB % 16 == 0 ? Stager<16, MAXP>::CAP : RB % 4 == 0 ? Stager<4, MAXP>::CAP : Stager<1, MAXP>::CAP;
+}
+
 bool solve_supported(int na, int fmt) {
   const int RB = na * efmt_bytes(fmt);
-  const int cap = RB % 16 == 0 ? Stager<16>::CAP : RB % 4 == 0 ? Stager<4>::CAP : Stager<1>::CAP;
+  const int cap = na <= kSolveThreads ? stage_cap<8>(RB) : stage_cap<4>(RB);   // the stagers of J = 1 and 2
   return na >= 1 && na <= 2 * kSolveThreads && RB <= cap;
 }
 

@@ -14,17 +14,22 @@ namespace epic {
 //   tap   P(t) = sum_a c_a E_a(t), c_a = A_a(k0) / (Na g_a)   (one wave per row)
 //   corr  K_a += E_a(t) conj(P(t)),  Q_a += |E_a(t)|^2       (threads over
 //         antenna x row-group; row-group partials meet by lane shuffles)
-// and at the end of each interval the FP64 damped update.
+// and at the end of each interval the damped update.  The whole recursion
+// (c, P, K, Q and the update) is FP64: where the calibrator is weak the first
+// intervals of the recursion amplify a relative perturbation of the tap by
+// up to 1e4, so FP32 rounding there would move the converged gains by 1e-3.
+// The E-fields are integers (or FP32) and enter exactly.
 // ---------------------------------------------------------------------------
 constexpr int kSolveThreads = 1024;
-constexpr int kSolveChunkBytes = 16384;
+constexpr int kSolveChunkBytes = 32768;   // a whole interval of most arrays: one load latency per interval
 constexpr int kSolveMaxRows = 1024;
 
-// One thread's share of a chunk copy, PS bytes per piece.
-template <int PS>
+// One thread's share of a chunk copy, PS bytes per piece, at most MAXP
+// pieces (registers) per thread.
+template <int PS, int MAXP>
 struct Stager {
   static constexpr int PPT0 = kSolveChunkBytes / (kSolveThreads * PS);
-  static constexpr int PPT = PPT0 < 4 ? PPT0 : 4;                      // pieces per thread
+  static constexpr int PPT = PPT0 < MAXP ? PPT0 : MAXP;               // pieces per thread
   static constexpr int CAP = kSolveThreads * PS * PPT;                 // bytes per chunk
   static constexpr int WPP = PS >= 4 ? PS / 4 : 1;                     // 32-bit words per piece
   uint32_t v[PPT * WPP];
@@ -72,25 +77,26 @@ struct Stager {
 
 // J = antennas per thread slot (Na <= 1024 * J), PS = chunk piece size.
 // LDS of one solve workgroup: two chunk buffers, the taps of a chunk and the
-// FP32 coefficients c_a (up to 2 * kSolveThreads antennas).
+// coefficients c_a (up to 2 * kSolveThreads antennas), both FP64.
 struct SolveSmem {
   static constexpr int P_OFF = 2 * kSolveChunkBytes;
-  static constexpr int C_OFF = P_OFF + kSolveMaxRows * 8;
-  static constexpr int BYTES = C_OFF + 2 * kSolveThreads * 8;
+  static constexpr int C_OFF = P_OFF + kSolveMaxRows * 16;
+  static constexpr int BYTES = C_OFF + 2 * kSolveThreads * 16;
 };
 
 template <int J, int PS>
 __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t* smem) {
   uint8_t (*chunk)[kSolveChunkBytes] = reinterpret_cast<uint8_t (*)[kSolveChunkBytes]>(smem);
-  float2* P_l = reinterpret_cast<float2*>(smem + SolveSmem::P_OFF);
-  float2* c_l = reinterpret_cast<float2*>(smem + SolveSmem::C_OFF);
+  double2* P_l = reinterpret_cast<double2*>(smem + SolveSmem::P_OFF);
+  double2* c_l = reinterpret_cast<double2*>(smem + SolveSmem::C_OFF);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int nwaves = kSolveThreads / 64;
   const int bpe = efmt_bytes(a.fmt);
   const int RB = a.Na * bpe;
   const int64_t rowstride = int64_t(a.F) * RB;
   const uint8_t* ebase = a.efield + int64_t(f) * RB;
-  int rpc = Stager<PS>::CAP / RB;
+  using Stage = Stager<PS, J == 1 ? 8 : 4>;
+  int rpc = Stage::CAP / RB;
   rpc = rpc < kSolveMaxRows ? rpc : kSolveMaxRows;
 
   // thread -> (antenna slot, row group); row groups of one antenna are adjacent lanes
@@ -100,19 +106,20 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
   const int rg = tid % RG;
   const int a0 = tid / RG;
 
-  double2 g[J], A[J];
+  double2 g[J], A[J], D[J];   // D is loaded once: the per-interval update must not wait on memory
   uint8_t hold[J];
   uint32_t st[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int an = a0 + NaP * j;
-    g[j] = A[j] = make_double2(0.0, 0.0);
+    g[j] = A[j] = D[j] = make_double2(0.0, 0.0);
     hold[j] = 0;
     st[j] = 0u;
     if (an < a.Na) {
       const int64_t ia = int64_t(f) * a.Na + an;
       g[j] = a.gains[ia];
       A[j] = a.A[ia];
+      D[j] = a.D[ia];
       hold[j] = a.hold[ia];
       if (a.g_hist && rg == 0) a.g_hist[ia] = g[j];
     }
@@ -123,7 +130,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
     const int64_t t0 = int64_t(n) * a.t_cal;
     return int(min(a.t_cal, a.n_t - t0));
   };
-  Stager<PS> stg;
+  Stage stg;
   int cur_buf = 0;
   {
     const int nr = min(rpc, interval_len(0));
@@ -144,7 +151,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
           double2 u = zrecip(g[j]);
           if (hold[j] & kHoldFlagged) u = make_double2(0.0, 0.0);
           const double2 c = zmul(A[j], u);
-          c_l[an] = make_float2(float(c.x / a.na_eff), float(c.y / a.na_eff));
+          c_l[an] = make_double2(c.x / a.na_eff, c.y / a.na_eff);
           a.u_hist[(int64_t(n) * a.F + f) * a.Na + an] = make_float2(float(u.x), float(u.y));
         }
       }
@@ -169,11 +176,19 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
       // tapped pixel of each row
       for (int r = wave; r < nr; r += nwaves) {
         const uint8_t* row = ch + r * RB;
-        float2 p = make_float2(0.f, 0.f);
-        for (int an = lane; an < a.Na; an += 64) p = cadd(p, cmul(c_l[an], load_sample(row, an, a.fmt)));
+        double px = 0.0, py = 0.0;
+        for (int an = lane; an < a.Na; an += 64) {
+          const float2 e = load_sample(row, an, a.fmt);
+          const double2 c = c_l[an];
+          px = fma(c.x, double(e.x), fma(-c.y, double(e.y), px));
+          py = fma(c.x, double(e.y), fma(c.y, double(e.x), py));
+        }
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) p = cadd(p, shfl_xor2(p, m));
-        if (lane == 0) P_l[r] = p;
+        for (int m = 32; m >= 1; m >>= 1) {
+          px += __shfl_xor(px, m);
+          py += __shfl_xor(py, m);
+        }
+        if (lane == 0) P_l[r] = make_double2(px, py);
       }
       __syncthreads();
       // correlation with the uncalibrated E-fields
@@ -181,17 +196,18 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
       for (int j = 0; j < J; ++j) {
         const int an = a0 + NaP * j;
         if (an < a.Na) {
-          float kx = 0.f, ky = 0.f, q = 0.f;
+          double kx = 0.0, ky = 0.0, q = 0.0;
           for (int r = rg; r < nr; r += RG) {
             const float2 e = load_sample(ch + r * RB, an, a.fmt);
-            const float2 p = P_l[r];
-            kx += e.x * p.x + e.y * p.y;
-            ky += e.y * p.x - e.x * p.y;
-            q += e.x * e.x + e.y * e.y;
+            const double ex = e.x, ey = e.y;
+            const double2 p = P_l[r];
+            kx = fma(ex, p.x, fma(ey, p.y, kx));
+            ky = fma(ey, p.x, fma(-ex, p.y, ky));
+            q = fma(ex, ex, fma(ey, ey, q));
           }
-          Kx[j] += double(kx);
-          Ky[j] += double(ky);
-          Q[j] += double(q);
+          Kx[j] += kx;
+          Ky[j] += ky;
+          Q[j] += q;
         }
       }
       if (have_next) stg.store(chunk[cur_buf ^ 1], nr_nx, RB, tid);
@@ -214,7 +230,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
       const int an = a0 + NaP * j;
       if (an < a.Na) {
         const double2 gn = epical_step(make_double2(Kx[j] * inv_n, Ky[j] * inv_n), Q[j] * inv_n, A[j],
-                                       a.D[int64_t(f) * a.Na + an], g[j], hold[j], a.na_eff, a.gamma, &st[j]);
+                                       D[j], g[j], hold[j], a.na_eff, a.gamma, &st[j]);
         g[j] = gn;
         if (a.g_hist && rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = gn;
       }

@@ -373,7 +373,9 @@ def config_hera(seed: int = 3, n_chan: int = 512, n_samples: int = 2000, **over)
     """HERA shape: 350 antennas on a 14 m hexagonal lattice, 8+8-bit E-fields,
     channels across 100-200 MHz, 128x128 grid of 2.5 m cells (origin offset a
     quarter cell), 2x2 kernel, calibrator carrying 10% of the sky power plus
-    100 power-law sources, gains every 100 samples."""
+    100 power-law sources (fluxes 1..10, over the visible sky, all fainter
+    than the calibrator), receiver noise equal to the sky power, gains every
+    100 samples."""
     s_lay, s_g, s_sky, _ = (_rng(k) for k in _streams(seed))
     Na, N, dx = 350, 128, 2.5
     ant = layout_hex(Na, 14.0)
@@ -382,8 +384,8 @@ def config_hera(seed: int = 3, n_chan: int = 512, n_samples: int = 2000, **over)
     x0 = _grid_for_disk(140.0, N, dx, 0.25)
     arr = ArraySpec(ant_xy=ant, freq_hz=freq, nx=N, ny=N, dx=dx, dy=dx, x0=x0, y0=x0,
                     kernel=2, efmt=FMT_CI8)
-    lm = random_disk_lm(s_sky, 100, 0.25)
-    S = powerlaw_flux(s_sky, 100, 1.0, 100.0)
+    lm = random_disk_lm(s_sky, 100, 0.9)
+    S = powerlaw_flux(s_sky, 100, 1.0, 10.0)
     cal = 0.1 / 0.9 * S.sum()
     cal_lm = random_disk_lm(s_sky, 1, 0.1)[0]
     src = np.concatenate([np.array([[cal_lm[0], cal_lm[1], cal]]), np.column_stack([lm, S])])

@@ -206,10 +206,10 @@ def test_run_lwa_full_size_sampled_channels(cuda):
     assert np.all(np.isfinite(got["image"])) and np.all(got["status"] == 0)
 
 
-@pytest.mark.parametrize("n", [32, 128])
-def test_fixed_gain_image(cuda, n):
+@pytest.mark.parametrize("n,na", [(32, 48), (64, 180), (128, 48)])
+def test_fixed_gain_image(cuda, n, na):
     torch = _torch()
-    wl = synth.config_small(n=n, n_chan=2, n_samples=77)
+    wl = synth.config_small(n=n, n_ant=na, n_chan=2, n_samples=77)
     a = wl.array
     packed = synth.make_efield(wl)
     g = synth.random_gains(3, 2, a.n_ant)

@@ -787,7 +787,7 @@ static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64
 struct RunLayout {
   int64_t n_int;
   int splits;
-  size_t u_off, p_off;
+  size_t u_off, p_off, gh_off;   // gh_off: gain history when the caller passes none
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -862,15 +862,22 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
     sa[i] = epic::SolveArgs{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt, ap.t_cal,
                             int(lay[i].n_int), ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma,
                             reinterpret_cast<double2*>(gains[i]), reinterpret_cast<float2*>(scr + lay[i].u_off),
-                            gain_hist ? reinterpret_cast<double2*>(gain_hist[i]) : nullptr,
+                            gain_hist ? reinterpret_cast<double2*>(gain_hist[i])
+                                      : reinterpret_cast<double2*>(scr + lay[i].gh_off),
                             ant_status ? ant_status[i] : nullptr};
   }
+  // FP32 u of every interval from the gain history the solve wrote
+  auto hist_to_u = [&](int i) -> hipError_t {
+    const HostArray& h = plan->arrays[i].h;
+    return epic::launch_hist_to_u(sa[i].g_hist, plan->arrays[i].d_hold, lay[i].n_int, h.F, h.na, sa[i].u_hist, s);
+  };
   if (!batched) {
     for (int i = 0; i < na_arr; ++i) {
       ArrayPlan& ap = plan->arrays[i];
       {
         Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
         hipError_t e = epic::launch_solve(sa[i], s);
+        if (e == hipSuccess) e = hist_to_u(i);
         if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
       }
       int rc = image_pass(plan, ap, efield[i], n_samples, reinterpret_cast<float2*>(scr + lay[i].u_off), ap.t_cal,
@@ -901,6 +908,10 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
         hipError_t e = epic::launch_solve(sa[i], s);
         if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
       }
+    }
+    for (int i = 0; i < na_arr; ++i) {
+      hipError_t e = hist_to_u(i);
+      if (e != hipSuccess) return hip_fail(e, "gain history conversion launch");
     }
   }
   // imaging: one persistent launch over every array's work items
@@ -970,6 +981,8 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     need += align256(size_t(lay[i].n_int) * ap.h.F * ap.h.na * sizeof(float2));
     lay[i].p_off = need;
     need += align256(size_t(lay[i].splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float));
+    lay[i].gh_off = need;
+    need += align256(size_t(lay[i].n_int + 1) * ap.h.F * ap.h.na * sizeof(double2));
     all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
   const bool batched = all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));

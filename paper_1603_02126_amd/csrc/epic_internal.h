@@ -65,8 +65,8 @@ struct SolveArgs {
   const uint8_t* hold;      // [F][Na] kHold* bits
   double na_eff, gamma;
   double2* gains;           // [F][Na] in/out
-  float2* u_hist;           // [n_int][F][Na]
-  double2* g_hist;          // [n_int+1][F][Na] or null
+  float2* u_hist;           // [n_int][F][Na] (written by launch_hist_to_u from g_hist)
+  double2* g_hist;          // [n_int+1][F][Na], required
   uint32_t* status;         // [F][Na] or null
 };
 
@@ -159,6 +159,9 @@ hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, do
                          float* image, hipStream_t s);
 bool solve_supported(int na, int fmt);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// u_hist[n] = 1 / g_hist[n] (FP64, rounded to FP32; zero for flagged antennas), n < n_int
+hipError_t launch_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_int, int F, int Na, float2* u_hist,
+                            hipStream_t s);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 hipError_t launch_adjoint(int N, const AdjointArgs& a, hipStream_t s);
 hipError_t launch_adjoint_reduce(const double2* partial, int splits, int F, int Na,

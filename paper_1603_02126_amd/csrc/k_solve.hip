@@ -79,6 +79,23 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   if (a.Na <= kSolveThreads) return launch_solve_j<1>(a, s);
   return launch_solve_j<2>(a, s);
 }
+__global__ __launch_bounds__(256) void k_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_elem,
+                                                   int64_t per_int, float2* u_hist) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n_elem) return;
+  double2 u = zrecip(g_hist[i]);
+  if (hold[i % per_int] & kHoldFlagged) u = make_double2(0.0, 0.0);
+  u_hist[i] = make_float2(float(u.x), float(u.y));
+}
+
+hipError_t launch_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_int, int F, int Na, float2* u_hist,
+                            hipStream_t s) {
+  const int64_t per = int64_t(F) * Na, n = n_int * per;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist_to_u, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, g_hist, hold, n, per, u_hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(a.F), dim3(256), 0, s, a);
   return hipGetLastError();

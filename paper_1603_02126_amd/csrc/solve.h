@@ -14,7 +14,11 @@ namespace epic {
 //   tap   P(t) = sum_a c_a E_a(t), c_a = A_a(k0) / (Na g_a)   (one wave per row)
 //   corr  K_a += E_a(t) conj(P(t)),  Q_a += |E_a(t)|^2       (threads over
 //         antenna x row-group; row-group partials meet by lane shuffles)
-// and at the end of each interval the damped update.  The whole recursion
+// and at the end of each interval the damped update.  The only global
+// stores are the gain history (its data registers stay live for a whole
+// interval, so no store ever has to drain before the next interval's
+// prefetch); the FP32 u = 1/g of every interval is derived from that
+// history afterwards (launch_hist_to_u).  The whole recursion
 // (c, P, K, Q and the update) is FP64: where the calibrator is weak the first
 // intervals of the recursion amplify a relative perturbation of the tap by
 // up to 1e4, so FP32 rounding there would move the converged gains by 1e-3.
@@ -37,20 +41,22 @@ struct Stager {
                                        int RB, int tid) {
     const int per_row = RB / PS;
     const int total = nrows * per_row;
+    // every piece is loaded (pieces past the chunk re-read its first piece)
+    // so that the loads are not under branches: the next chunk's loads then
+    // stay in flight while the current chunk is processed
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      const int p = tid + k * kSolveThreads;
-      if (p < total) {
-        const int r = p / per_row, c = p - r * per_row;
-        const uint8_t* src = ebase + (t_first + r) * rowstride + c * PS;
-        if constexpr (PS == 16) {
-          const uint4 w = *reinterpret_cast<const uint4*>(src);
-          v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
-        } else if constexpr (PS == 4) {
-          v[k] = *reinterpret_cast<const uint32_t*>(src);
-        } else {
-          v[k] = *src;
-        }
+      const int p0 = tid + k * kSolveThreads;
+      const int p = p0 < total ? p0 : 0;
+      const int r = p / per_row, c = p - r * per_row;
+      const uint8_t* src = ebase + (t_first + r) * rowstride + c * PS;
+      if constexpr (PS == 16) {
+        const uint4 w = *reinterpret_cast<const uint4*>(src);
+        v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
+      } else if constexpr (PS == 4) {
+        v[k] = *reinterpret_cast<const uint32_t*>(src);
+      } else {
+        v[k] = *src;
       }
     }
   }
@@ -74,6 +80,28 @@ struct Stager {
     }
   }
 };
+
+// DPP move of a double (two 32-bit halves); lanes without a source read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double(static_cast<long long>(static_cast<unsigned>(lo)) |
+                              (static_cast<long long>(hi) << 32));
+}
+
+// Sum over the 64 lanes of a wave, complete in lane 63: shifted partial
+// sums within each row of 16 lanes, then the row totals by row broadcasts.
+__device__ __forceinline__ double wave_sum_lane63(double x) {
+  x += dpp_f64<0x111>(x);         // row_shr:1
+  x += dpp_f64<0x112>(x);         // row_shr:2
+  x += dpp_f64<0x114>(x);         // row_shr:4
+  x += dpp_f64<0x118>(x);         // row_shr:8: lane 15 of each row holds the row
+  x += dpp_f64<0x142, 0xa>(x);    // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xc>(x);    // row_bcast:31 into rows 2 and 3
+  return x;
+}
 
 // J = antennas per thread slot (Na <= 1024 * J), PS = chunk piece size.
 // LDS of one solve workgroup: two chunk buffers, the taps of a chunk and the
@@ -121,7 +149,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
       A[j] = a.A[ia];
       D[j] = a.D[ia];
       hold[j] = a.hold[ia];
-      if (a.g_hist && rg == 0) a.g_hist[ia] = g[j];
+      if (rg == 0) a.g_hist[ia] = g[j];
     }
   }
 
@@ -152,7 +180,6 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
           if (hold[j] & kHoldFlagged) u = make_double2(0.0, 0.0);
           const double2 c = zmul(A[j], u);
           c_l[an] = make_double2(c.x / a.na_eff, c.y / a.na_eff);
-          a.u_hist[(int64_t(n) * a.F + f) * a.Na + an] = make_float2(float(u.x), float(u.y));
         }
       }
     }
@@ -183,12 +210,9 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
           px = fma(c.x, double(e.x), fma(-c.y, double(e.y), px));
           py = fma(c.x, double(e.y), fma(c.y, double(e.x), py));
         }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-          px += __shfl_xor(px, m);
-          py += __shfl_xor(py, m);
-        }
-        if (lane == 0) P_l[r] = make_double2(px, py);
+        px = wave_sum_lane63(px);
+        py = wave_sum_lane63(py);
+        if (lane == 63) P_l[r] = make_double2(px, py);
       }
       __syncthreads();
       // correlation with the uncalibrated E-fields
@@ -197,6 +221,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
         const int an = a0 + NaP * j;
         if (an < a.Na) {
           double kx = 0.0, ky = 0.0, q = 0.0;
+#pragma unroll 4
           for (int r = rg; r < nr; r += RG) {
             const float2 e = load_sample(ch + r * RB, an, a.fmt);
             const double ex = e.x, ey = e.y;
@@ -232,7 +257,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
         const double2 gn = epical_step(make_double2(Kx[j] * inv_n, Ky[j] * inv_n), Q[j] * inv_n, A[j],
                                        D[j], g[j], hold[j], a.na_eff, a.gamma, &st[j]);
         g[j] = gn;
-        if (a.g_hist && rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = gn;
+        if (rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = gn;
       }
     }
   }

@@ -103,18 +103,31 @@ __device__ __forceinline__ void stage_frame(float2* epr, const Raw (&raw)[APL], 
 }
 
 // Grid the staged frame into `buf` (owned cells only; the rest stays zero).
+// Slots go in batches of B: the B table entries are loaded together, then
+// the B staged values, then the B cell stores -- the stores may alias the
+// loads as far as the compiler can tell, so without batching every slot
+// would wait for two LDS round trips.
+template <int B = 4>
 __device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const uint2* stab, int S, int L,
                                            int lam) {
   float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 4
-  for (int s = 0; s < S; ++s) {
-    const uint2 e = stab[s * L + lam];
-    const float2 ev = epr[e.x & kSlotAntMask];
-    const float w = __uint_as_float(e.y);
-    const bool first = int(e.x) < 0;
-    acc.x = fmaf(w, ev.x, first ? 0.f : acc.x);
-    acc.y = fmaf(w, ev.y, first ? 0.f : acc.y);
-    buf[(e.x >> kSlotCellShift) & kSlotCellMask] = acc;
+  for (int s0 = 0; s0 < S; s0 += B) {
+    uint2 e[B];
+    float2 ev[B];
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int s = s0 + k < S ? s0 + k : S - 1;
+      e[k] = stab[s * L + lam];
+    });
+    static_for<0, B>([&](auto kc) { ev[decltype(kc)::value] = epr[e[decltype(kc)::value].x & kSlotAntMask]; });
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const float w = __uint_as_float(e[k].y);
+      const bool first = int(e[k].x) < 0;
+      acc.x = fmaf(w, ev[k].x, first ? 0.f : acc.x);
+      acc.y = fmaf(w, ev[k].y, first ? 0.f : acc.y);
+      if (s0 + k < S) buf[(e[k].x >> kSlotCellShift) & kSlotCellMask] = acc;
+    });
   }
 }
 

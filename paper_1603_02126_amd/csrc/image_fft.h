@@ -110,8 +110,9 @@ struct PairSmem {
   static_assert(8 * 64 * 64 * 4 <= T_OFF, "the accumulator reduction reuses the wave areas");
 };
 
-template <int APL>
+template <int APL, int FMT>
 __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
   constexpr int N = 64, P = Geo<64>::PITCH, INFLIGHT = 8;
   using L = PairSmem<APL>;
   float2* lds = reinterpret_cast<float2*>(smem);
@@ -131,29 +132,37 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
   float2 v[N];
   uint32_t raw[APL];   // integer formats only: one packed sample per register
   const int64_t iters = (te - tb + INFLIGHT - 1) / INFLIGHT;
-  const int bpe = efmt_bytes(a.fmt);
-  // the packed samples of a frame are prefetched one frame ahead; u (constant
-  // over an interval, cache resident) is loaded when the frame is staged
+  constexpr int bpe = FMT == kCI4 ? 1 : 2;
+  // the packed samples of a frame are requested at the end of the previous
+  // frame; u (constant over an interval, cache resident) is loaded when the
+  // frame is staged
   auto fetch_raw = [&](int64_t t) {
     const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, a.fmt).x : 0u;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
     });
   };
   fetch_raw(tb + wave);
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t t = tb + it * INFLIGHT + wave;
+    // calibrate: all u loads are issued before any is used (one memory
+    // latency per frame)
     const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
+    float2 uu[APL];
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      if (an < a.Na) epr[an] = t < te ? cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, a.fmt), urow[an])
+      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+    });
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      if (an < a.Na) epr[an] = t < te ? cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, FMT),
+                                             uu[decltype(ic)::value])
                                       : make_float2(0.f, 0.f);
     });
-    fetch_raw(t + INFLIGHT);
     wave_lds_sync();
     // rows 0..31: grid, lanes 0..31 load their row and zero it
-    grid_frame(H, epr, stab, S0, N, lam);
+    grid_frame<8>(H, epr, stab, S0, N, lam);
     wave_lds_sync();
     if (lam < 32) {
       static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
@@ -161,7 +170,7 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     }
     wave_lds_sync();
     // rows 32..63
-    grid_frame(H, epr, stab + S0 * N, S1, N, lam);
+    grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
     wave_lds_sync();
     if (lam >= 32) {
       static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
@@ -172,6 +181,9 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     transpose64(v, H, lam);       // lane = column kx
     static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     fft_reg<N, +1>(v);            // along y
+    // the next frame's samples are requested here rather than at staging:
+    // their registers would otherwise stay live through both FFTs
+    fetch_raw(t + INFLIGHT);
     static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
   }
 

@@ -38,11 +38,11 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   image_item<N, APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
-template <int APL>
+template <int APL, int FMT>
 __global__ __launch_bounds__(kPairThreads) void k_image_pair(ImageArgs a) {
   static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
   __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
-  image_item_pair<APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
+  image_item_pair<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
 template <int R>
@@ -198,7 +198,8 @@ struct LaunchImage {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
     if constexpr (N == 64 && APL == 4) {
       if (pair_engine(a, N)) {
-        hipLaunchKernelGGL((k_image_pair<APL>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair<APL, kCI4>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_image_pair<APL, kCI8>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
         return hipGetLastError();
       }
     }

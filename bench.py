@@ -73,8 +73,10 @@ def measured_traffic(workload_name):
 
 def dft_mfma_flops_per_frame(n):
     """Executed matrix-core flops of the split-precision DFT-GEMM per frame:
-    two complex N x N x N products, four real GEMMs each, three split terms."""
-    return 2 * 4 * 3 * 2 * n ** 3
+    two complex M x M x M products, four real GEMMs each, three split terms,
+    for each of the (n / M)^2 residue classes of 64 x 64 (M = min(n, 64))."""
+    m = min(n, 64)
+    return (n // m) ** 2 * 2 * 4 * 3 * 2 * m ** 3
 
 
 def imaging_flops_per_frame(n, na, k2):
@@ -272,7 +274,7 @@ def bench_single(args, dev):
     frames = a.n_chan * wl.n_samples
     forms = {}
     if not args.no_forms:
-        if a.nx in (32, 64):
+        if a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512):
             # form 1: split-precision DFT-GEMM on the matrix cores, same workload
             plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2})
             img_d = torch.zeros_like(img)
@@ -288,7 +290,8 @@ def bench_single(args, dev):
                 "_image": img_d}
             plan_d.close()
         else:
-            forms["dft_gemm_fp16_split"] = {"supported": False, "reason": "the DFT-GEMM form covers 32x32 and 64x64"}
+            forms["dft_gemm_fp16_split"] = {"supported": False,
+                                             "reason": "the DFT-GEMM form covers arrays of at most 512 antennas"}
         # form 2: batched launches captured in a hipGraph, after autotuning
         plan_g = new_plan([wl])
         tuning = plan_g.autotune([e], wl.n_samples)

@@ -144,7 +144,10 @@ int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* mod
 /* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)
  *   EPIC_OPT_TRANSFORM   0 = FFT, 1 = FFT (FP32), 2 = DFT-GEMM (FP16 hi+lo split on
- *                        the matrix cores, FP32 accumulation; grids 32 and 64)
+ *                        the matrix cores, FP32 accumulation; grids 32 and 64,
+ *                        and 128 and 256 as residue classes of 64 x 64 DFT-GEMMs
+ *                        for arrays of at most 512 antennas; those are imaged
+ *                        with one launch per array even when batched)
  *   EPIC_OPT_TIMING      1 = record HIP events around each kernel (see below)
  *   EPIC_OPT_BATCH       0 = batched when the plan has several arrays, 1 = always
  *                        batched, 2 = never.  Batched, epic_run makes one launch per
@@ -177,7 +180,8 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 
 /* Autotuner: for every array, time the imaging launch of the given E-field
  * stream (n_samples samples) with each candidate transform (FFT; DFT-GEMM for
- * grids 32 and 64) and time-split count, and keep the fastest for later runs.
+ * the grids and arrays it covers) and time-split count, and keep the fastest for
+ * later runs.
  * Synchronous (waits for the device); efield: one device pointer per array. */
 int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples,
                        epic_stream_t stream);

@@ -760,14 +760,19 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "epical_update launch");
 }
 
+// Slot schedule of the DFT-GEMM engine: its own transposed table for N <= 64,
+// the residue-class table for N = 128, 256.
+static const uint2* dft_slots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.d_slots : ap.d_slots_dft; }
+static int dft_nslots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.n_slots : ap.n_slots_dft; }
+
 static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64_t n_samples, const float2* u,
                       int64_t t_cal, float* image, hipStream_t s, float* partial, int splits, bool timed = true) {
   const HostArray& h = ap.h;
   const int N = h.nx;
   const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
-  const bool dft = tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft);
+  const bool dft = tr == 2 && epic::dft_supported(N, h.na, dft_nslots(ap));
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
-               dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, splits, partial,
+               dft ? dft_slots(ap) : ap.d_slots, dft ? dft_nslots(ap) : ap.n_slots, splits, partial,
                ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
@@ -795,11 +800,12 @@ static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 static int engine_of(epic_plan_t plan, const ArrayPlan& ap) {
   const HostArray& h = ap.h;
   const int N = h.nx;
+  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
   if (N >= 128) {
+    if (tr == 2 && epic::dft_supported(N, h.na, ap.n_slots)) return epic::engine_code(epic::kEngDftCls, N, N / 64);
     const int v = epic::cls_variant(h.na, ap.n_slots);
     return epic::engine_code(v == 2 ? epic::kEngClsBig : epic::kEngCls, N, N / 64);
   }
-  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
   const int apl = (h.na + 63) / 64 <= 2 ? 2 : (h.na + 63) / 64 <= 4 ? 4 : 8;
   if (tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft)) return epic::engine_code(epic::kEngDft, N, apl);
   const int aplf = (h.na + N - 1) / N <= 2 ? 2 : (h.na + N - 1) / N <= 4 ? 4 : 8;
@@ -1128,7 +1134,7 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
     if (!efield[i]) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
     const HostArray& h = ap.h;
     std::vector<int> trs{1};
-    if (epic::dft_supported(h.nx, h.na, ap.n_slots_dft)) trs.push_back(2);
+    if (epic::dft_supported(h.nx, h.na, dft_nslots(ap))) trs.push_back(2);
     const int base = pick_splits(plan, h.F, n_samples, h.nx, 0);
     std::vector<int> sps;
     for (int c : {base / 2, base, 2 * base, 4 * base}) {

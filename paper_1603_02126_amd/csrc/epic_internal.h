@@ -104,7 +104,7 @@ struct AdjointArgs {
 
 // Batched execution over several arrays (one launch per stage).
 constexpr int kMaxBatch = 16;
-enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3 };
+enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3, kEngDftCls = 4 };   // kEngDftCls: not batched
 // Engine code of an array: 100 * engine + (N / 32) * 10 + (APL or R).
 inline int engine_code(int engine, int N, int param) { return 100 * engine + (N / 32) * 10 + param; }
 

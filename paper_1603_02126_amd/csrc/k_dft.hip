@@ -1,4 +1,5 @@
-// HIP kernels (gfx950): split-precision DFT-GEMM imaging (see image_dft.h).
+// HIP kernels (gfx950): split-precision DFT-GEMM imaging (see image_dft.h);
+// grids of 128 and 256 by residue classes of 64 x 64 DFT-GEMMs.
 #include "image_dft.h"
 
 namespace epic {
@@ -9,7 +10,18 @@ __global__ __launch_bounds__(256) void k_image_dft(ImageArgs a) {
   dft_item<N, APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
+template <int R>
+__global__ __launch_bounds__(256) void k_image_dft_cls(ImageArgs a) {
+  __shared__ __align__(16) uint8_t smem[DftClsSmem<R>::BYTES];
+  constexpr int CP = R * R / 2;   // class pairs
+  const int rest = blockIdx.x / a.F;
+  dft_cls_item<R>(a, blockIdx.x % a.F, rest % CP, rest / CP, smem);
+}
+
+// n_slots: the transposed 64-lane schedule for N <= 64, the residue-class
+// schedule for N = 128, 256.
 bool dft_supported(int N, int na, int n_slots) {
+  if (N == 128 || N == 256) return na <= kDftClsMaxAnt && n_slots <= kDftTabSlots;
   return (N == 32 || N == 64) && na <= 8 * 64 && n_slots <= kDftTabSlots;
 }
 
@@ -24,6 +36,10 @@ hipError_t launch_image_dft(int N, const ImageArgs& a, hipStream_t s) {
     if (apl <= 2) hipLaunchKernelGGL((k_image_dft<32, 2>), grid, dim3(256), 0, s, a);
     else if (apl <= 4) hipLaunchKernelGGL((k_image_dft<32, 4>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_image_dft<32, 8>), grid, dim3(256), 0, s, a);
+  } else if (N == 128) {
+    hipLaunchKernelGGL((k_image_dft_cls<2>), dim3(a.F * 2 * a.splits), dim3(256), 0, s, a);
+  } else if (N == 256) {
+    hipLaunchKernelGGL((k_image_dft_cls<4>), dim3(a.F * 8 * a.splits), dim3(256), 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }

@@ -1,6 +1,7 @@
 """GPU parity of the split-precision DFT-GEMM imaging (FP16 hi+lo operands on
 the matrix cores, FP32 accumulation) against the FP64 oracle, at the same
-tolerances as the FP32 FFT path."""
+tolerances as the FP32 FFT path: 32 x 32 and 64 x 64 directly, 128 x 128 and
+256 x 256 as residue classes of 64 x 64 transforms."""
 import numpy as np
 import pytest
 
@@ -16,6 +17,9 @@ pytestmark = pytest.mark.gpu
     (64, synth.FMT_CI4, 2, 200, 301, 100),
     (32, synth.FMT_CF32, 1, 32, 64, 1),
     (64, synth.FMT_CI8, 2, 300, 90, 40),
+    (128, synth.FMT_CI8, 2, 150, 70, 30),     # residue classes of 64 x 64 DFT-GEMMs
+    (256, synth.FMT_CI4, 2, 300, 33, 20),
+    (128, synth.FMT_CF32, 1, 40, 25, 25),
 ])
 def test_dft_gemm_run_matches_oracle(cuda, n, efmt, kernel, na, n_samples, t_cal):
     wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_samples=n_samples, t_cal=t_cal)
@@ -46,3 +50,18 @@ def test_dft_gemm_lwa_full_size_sampled(cuda):
     assert image_err(got["image"][chans], ref["image"]).max() <= IMAGE_RTOL
     assert image_err(got["image"], fft["image"]).max() <= 2 * IMAGE_RTOL
     np.testing.assert_array_equal(got["gains"], fft["gains"])   # same solve kernel
+
+
+def test_dft_gemm_hera_full_size_sampled(cuda):
+    """HERA-shaped workload at full size through the residue-class DFT-GEMM
+    (128 x 128, 350 antennas); the oracle checks one channel and the FFT path
+    all of them."""
+    wl = synth.config_hera()
+    packed = synth.make_efield(wl, threads=16)
+    got = gpu_run(wl, packed, cuda, transform=2)
+    fft = gpu_run(wl, packed, cuda, transform=1)
+    chans = [201]
+    ref = oracle_run(wl, packed[:, chans], channels=chans)
+    assert image_err(got["image"][chans], ref["image"]).max() <= IMAGE_RTOL
+    assert image_err(got["image"], fft["image"]).max() <= 2 * IMAGE_RTOL
+    np.testing.assert_array_equal(got["gains"], fft["gains"])

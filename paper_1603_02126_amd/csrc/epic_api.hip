@@ -268,7 +268,8 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
 // grouped by sub-cell q = j mod 64 and sub-cells are balanced over 64 lanes;
 // each slot keeps the full cell j = 64 p + q so that the kernel can apply the
 // class phase exp(+2 pi i j.c / N).
-int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table) {
+// Sub-cell rows y0 <= qy < y1 only when y1 > y0 (the codes keep the full qy).
+int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int y0 = 0, int y1 = 0) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
@@ -279,6 +280,7 @@ int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table) {
     for (int k = 0; k < h.k2; ++k) {
       const size_t q = size_t(a) * h.k2 + k;
       if (w[q] == 0.0) continue;
+      if (y1 > y0 && (iy[q] % 64 < y0 || iy[q] % 64 >= y1)) continue;
       sub[size_t(iy[q] % 64) * 64 + ix[q] % 64].push_back({a, ix[q], iy[q], float(w[q])});
     }
   }
@@ -604,6 +606,13 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       std::vector<uint32_t> tab;
       ap.n_slots = build_slots_cls(ap.h, tab);
       rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      if (!rc) {
+        std::vector<uint32_t> hi;
+        ap.n_slots_h0 = build_slots_cls(ap.h, tab, 0, 32);
+        ap.n_slots_h1 = build_slots_cls(ap.h, hi, 32, 64);
+        tab.insert(tab.end(), hi.begin(), hi.end());
+        rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      }
     }
     if (rc) {
       epic_plan_destroy(p);

@@ -26,8 +26,10 @@ struct ImageArgs {
   int n_slots;
   int splits;               // workgroups per channel
   float* partial;           // [splits][F][N*N]
-  // 64 x 64 only: schedule of the half-frame gridding (rows 0..31, then rows
-  // 32..63, each re-based to row 0, 64 lanes); null when not built
+  // schedule of the half-frame gridding (64 lanes): rows 0..31, then rows
+  // 32..63; for 64 x 64 the cell offsets are re-based to row 0, for the
+  // residue-class engines the codes keep the sub-cell (the kernel re-bases);
+  // null when not built
   const uint2* slots_h = nullptr;
   int n_slots_h0 = 0, n_slots_h1 = 0;
 };

@@ -20,6 +20,7 @@
 // per frame).
 #pragma once
 #include "engine.h"
+#include "xpose.h"
 
 namespace epic {
 
@@ -123,6 +124,164 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
     constexpr int y = decltype(yc)::value;
     out[(R * y + cy) * N + R * lane + cx] = acc[y];
   });
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Residue-class engine with two waves per SIMD (integer E-fields, Na <= 512).
+//
+// Eight waves: two frames (samples t, t + 1) x four classes of the class
+// group.  Each wave grids its class of its frame through half a 64 x 64 frame
+// (sub-cell rows 0..31, then 32..63, two schedules built on the host), runs
+// the row FFTs, transposes in registers (xpose.h, the half frame as staging)
+// and runs the column FFTs, as the 64 x 64 paired engine does.  The E' of the
+// two frames is staged once per frame by its four waves; two workgroup
+// barriers per pair of samples order the staging against the gridding.
+// Waves w and w + 4 image the same class and are summed at the end.
+// ---------------------------------------------------------------------------
+constexpr int kClsPairThreads = 512;
+
+template <int R>
+struct ClsPairSmem {
+  static constexpr int N = 64 * R;
+  static constexpr int HALF = 32 * Geo<64>::PITCH;               // float2 per wave
+  static constexpr int E_OFF = 8 * HALF * 8;                     // bytes
+  static constexpr int TW_OFF = E_OFF + 2 * kClsMaxAnt * 8;
+  static constexpr int T_OFF = TW_OFF + N * 8;
+  static constexpr int TAB_SLOTS = (kLdsBytes - T_OFF) / (64 * 8);
+  static constexpr int BYTES = T_OFF + TAB_SLOTS * 64 * 8;
+  static_assert(HALF >= kXposeFloat2, "the transpose staging reuses the half frame");
+  static_assert(4 * 64 * 64 * 4 <= E_OFF, "the class reduction reuses the half frames");
+};
+
+// Grid sub-cell rows [32 hf, 32 hf + 32) of class (cx, cy) into the half
+// frame H (row qy - 32 hf), slots in batches of B.
+template <int R, int B>
+__device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, const float2* tw, const uint2* stab,
+                                              int S, int hf, int cx, int cy, int lam) {
+  constexpr int N = 64 * R, P = Geo<64>::PITCH;
+  float2 sum = make_float2(0.f, 0.f);
+  for (int s0 = 0; s0 < S; s0 += B) {
+    uint2 e[B];
+    float2 ev[B], ph[B];
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      e[k] = stab[(s0 + k < S ? s0 + k : S - 1) * 64 + lam];
+    });
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const uint32_t code = e[k].x;
+      const int jx = int((code >> 12) & 63) + 64 * int((code >> 24) & 3);
+      const int jy = int((code >> 18) & 63) + 64 * int((code >> 26) & 3);
+      ph[k] = tw[(jx * cx + jy * cy) & (N - 1)];
+      ev[k] = epr[code & kSlotAntMask];
+    });
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const uint32_t code = e[k].x;
+      const float w = __uint_as_float(e[k].y);
+      const float2 c = cmul(ev[k], make_float2(w * ph[k].x, w * ph[k].y));
+      const bool first = int(code) < 0;
+      sum.x = first ? c.x : sum.x + c.x;
+      sum.y = first ? c.y : sum.y + c.y;
+      const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
+      const int off = (code >> 30) & 1 ? (qy - 32 * hf) * P + qx : 64;
+      if (s0 + k < S) H[off] = sum;
+    });
+  }
+}
+
+template <int R, int FMT>
+__device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
+  static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
+  constexpr int N = 64 * R, P = Geo<64>::PITCH, NF = 64;
+  using L = ClsPairSmem<R>;
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int tid = threadIdx.x, lam = tid & 63, wave = tid >> 6;
+  const int fs = wave >> 2, ci = wave & 3;          // frame slot, class within the group
+  const int c = cg * 4 + ci, cx = c % R, cy = c / R;
+  const int gt = tid & 255;                         // thread within the frame's four waves
+  float2* H = lds + wave * L::HALF;
+  float2* epr = reinterpret_cast<float2*>(smem + L::E_OFF) + fs * kClsMaxAnt;
+  float2* tw = reinterpret_cast<float2*>(smem + L::TW_OFF);
+  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
+  const int S0 = a.n_slots_h0, S1 = a.n_slots_h1;
+  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
+  constexpr int bpe = FMT == kCI4 ? 1 : 2;
+  constexpr int APT = kClsMaxAnt / 256;             // antennas per staging thread
+
+  load_slot_table(stab, a.slots_h, S0 + S1, 64);
+  for (int k = tid; k < N; k += kClsPairThreads) {
+    double sn, cs;
+    sincospi(2.0 * double(k) / double(N), &sn, &cs);
+    tw[k] = make_float2(float(cs), float(sn));
+  }
+  if (lam < 32) static_for<0, NF>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+
+  float acc[NF];
+  static_for<0, NF>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  float2 v[NF];
+  uint32_t raw[APT];
+  auto fetch_raw = [&](int64_t t) {
+    const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
+    static_for<0, APT>([&](auto ic) {
+      const int an = gt + 256 * decltype(ic)::value;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
+    });
+  };
+  const int64_t iters = (te - tb + 1) / 2;
+  fetch_raw(tb + fs);
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t t = tb + 2 * it + fs;
+    // stage E' of this frame (its four waves)
+    const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
+    float2 uu[APT];
+    static_for<0, APT>([&](auto ic) {
+      const int an = gt + 256 * decltype(ic)::value;
+      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+    });
+    static_for<0, APT>([&](auto ic) {
+      const int an = gt + 256 * decltype(ic)::value;
+      if (an < a.Na) epr[an] = t < te ? cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, FMT),
+                                             uu[decltype(ic)::value])
+                                      : make_float2(0.f, 0.f);
+    });
+    __syncthreads();
+    grid_cls_half<R, 4>(H, epr, tw, stab, S0, 0, cx, cy, lam);
+    wave_lds_sync();
+    if (lam < 32) {
+      static_for<0, NF>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
+      static_for<0, NF>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    wave_lds_sync();
+    grid_cls_half<R, 4>(H, epr, tw, stab + S0 * 64, S1, 1, cx, cy, lam);
+    wave_lds_sync();
+    if (lam >= 32) {
+      static_for<0, NF>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
+      static_for<0, NF>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    __syncthreads();   // every wave is done with this pair's E'
+    fft_reg<NF, +1>(v);
+    transpose64(v, H, lam);
+    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    fft_reg<NF, +1>(v);
+    fetch_raw(t + 2);
+    static_for<0, NF>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+  }
+  // sum the two frame slots of each class, then write the class pixels
+  // (R y + cy, R kx + cx) with kx = lam
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+  if (fs == 1)
+    static_for<0, NF>([&](auto yc) { red[(ci * NF + decltype(yc)::value) * NF + lam] = acc[decltype(yc)::value]; });
+  __syncthreads();
+  if (fs == 0) {
+    float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
+    static_for<0, NF>([&](auto yc) {
+      constexpr int y = decltype(yc)::value;
+      out[(R * y + cy) * N + R * lam + cx] = acc[y] + red[(ci * NF + y) * NF + lam];
+    });
+  }
   __syncthreads();
 }
 

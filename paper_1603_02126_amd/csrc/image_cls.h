@@ -233,6 +233,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
   fetch_raw(tb + fs);
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t t = tb + 2 * it + fs;
+    __builtin_amdgcn_s_setprio(1);   // LDS-bound phases at raised priority (see the 64 x 64 paired engine)
     // stage E' of this frame (its four waves)
     const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
     float2 uu[APT];
@@ -261,9 +262,12 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
       static_for<0, NF>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
     }
     __syncthreads();   // every wave is done with this pair's E'
+    __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);
+    __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);
     static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);
     fetch_raw(t + 2);
     static_for<0, NF>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });

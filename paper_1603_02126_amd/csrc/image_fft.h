@@ -146,6 +146,10 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
   fetch_raw(tb + wave);
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t t = tb + it * INFLIGHT + wave;
+    // the LDS-bound phases (staging, gridding, transpose) run at a raised
+    // wave priority so that they advance while the other wave of the SIMD
+    // is in an FFT
+    __builtin_amdgcn_s_setprio(1);
     // calibrate: all u loads are issued before any is used (one memory
     // latency per frame)
     const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
@@ -177,9 +181,12 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
       static_for<0, N>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
     }
     wave_lds_sync();
+    __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along x: lane = row y
+    __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);       // lane = column kx
     static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along y
     // the next frame's samples are requested here rather than at staging:
     // their registers would otherwise stay live through both FFTs

@@ -11,7 +11,7 @@ namespace epic {
 // The packed E-fields of the channel stream through LDS in chunks of rows
 // (one row = one sample of all antennas), double buffered: the next chunk is
 // fetched into registers while the current one is processed.  Per chunk:
-//   tap   P(t) = sum_a c_a E_a(t), c_a = A_a(k0) / (Na g_a)   (one wave per row)
+//   tap   P(t) = sum_a c_a E_a(t), c_a = A_a(k0) / (Na g_a)   (16 lanes per row)
 //   corr  K_a += E_a(t) conj(P(t)),  Q_a += |E_a(t)|^2       (threads over
 //         antenna x row-group; row-group partials meet by lane shuffles)
 // and at the end of each interval the damped update.  The only global
@@ -91,15 +91,12 @@ __device__ __forceinline__ double dpp_f64(double x) {
                               (static_cast<long long>(hi) << 32));
 }
 
-// Sum over the 64 lanes of a wave, complete in lane 63: shifted partial
-// sums within each row of 16 lanes, then the row totals by row broadcasts.
-__device__ __forceinline__ double wave_sum_lane63(double x) {
-  x += dpp_f64<0x111>(x);         // row_shr:1
-  x += dpp_f64<0x112>(x);         // row_shr:2
-  x += dpp_f64<0x114>(x);         // row_shr:4
-  x += dpp_f64<0x118>(x);         // row_shr:8: lane 15 of each row holds the row
-  x += dpp_f64<0x142, 0xa>(x);    // row_bcast:15 into rows 1 and 3
-  x += dpp_f64<0x143, 0xc>(x);    // row_bcast:31 into rows 2 and 3
+// Sum over each row of 16 lanes, complete in the row's lane 15.
+__device__ __forceinline__ double row16_sum_lane15(double x) {
+  x += dpp_f64<0x111>(x);   // row_shr:1
+  x += dpp_f64<0x112>(x);   // row_shr:2
+  x += dpp_f64<0x114>(x);   // row_shr:4
+  x += dpp_f64<0x118>(x);   // row_shr:8
   return x;
 }
 
@@ -112,14 +109,13 @@ struct SolveSmem {
   static constexpr int BYTES = C_OFF + 2 * kSolveThreads * 16;
 };
 
-template <int J, int PS>
-__device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t* smem) {
+template <int J, int PS, int FMT>
+__device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uint8_t* smem) {
   uint8_t (*chunk)[kSolveChunkBytes] = reinterpret_cast<uint8_t (*)[kSolveChunkBytes]>(smem);
   double2* P_l = reinterpret_cast<double2*>(smem + SolveSmem::P_OFF);
   double2* c_l = reinterpret_cast<double2*>(smem + SolveSmem::C_OFF);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int nwaves = kSolveThreads / 64;
-  const int bpe = efmt_bytes(a.fmt);
+  const int tid = threadIdx.x;
+  constexpr int bpe = FMT == kCF32 ? 8 : FMT == kCI8 ? 2 : 1;
   const int RB = a.Na * bpe;
   const int64_t rowstride = int64_t(a.F) * RB;
   const uint8_t* ebase = a.efield + int64_t(f) * RB;
@@ -200,19 +196,27 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
       if (have_next) stg.load(ebase, rowstride, int64_t(n_nx) * a.t_cal + r_nx, nr_nx, RB, tid);
 
       const uint8_t* ch = chunk[cur_buf];
-      // tapped pixel of each row
-      for (int r = wave; r < nr; r += nwaves) {
-        const uint8_t* row = ch + r * RB;
-        double px = 0.0, py = 0.0;
-        for (int an = lane; an < a.Na; an += 64) {
-          const float2 e = load_sample(row, an, a.fmt);
-          const double2 c = c_l[an];
-          px = fma(c.x, double(e.x), fma(-c.y, double(e.y), px));
-          py = fma(c.x, double(e.y), fma(c.y, double(e.x), py));
+      // tapped pixel of each row: 16 lanes per row (antennas strided by 16),
+      // 64 rows per pass, sums within each 16-lane DPP row
+      {
+        const int q = tid & 15, rr = tid >> 4;
+        for (int rb = 0; rb < nr; rb += kSolveThreads / 16) {
+          const int r = rb + rr;
+          double px = 0.0, py = 0.0;
+          if (r < nr) {
+            const uint8_t* row = ch + r * RB;
+#pragma unroll 4
+            for (int an = q; an < a.Na; an += 16) {
+              const float2 e = load_sample(row, an, FMT);
+              const double2 c = c_l[an];
+              px = fma(c.x, double(e.x), fma(-c.y, double(e.y), px));
+              py = fma(c.x, double(e.y), fma(c.y, double(e.x), py));
+            }
+          }
+          px = row16_sum_lane15(px);
+          py = row16_sum_lane15(py);
+          if (q == 15 && r < nr) P_l[r] = make_double2(px, py);
         }
-        px = wave_sum_lane63(px);
-        py = wave_sum_lane63(py);
-        if (lane == 63) P_l[r] = make_double2(px, py);
       }
       __syncthreads();
       // correlation with the uncalibrated E-fields
@@ -223,7 +227,7 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
           double kx = 0.0, ky = 0.0, q = 0.0;
 #pragma unroll 4
           for (int r = rg; r < nr; r += RG) {
-            const float2 e = load_sample(ch + r * RB, an, a.fmt);
+            const float2 e = load_sample(ch + r * RB, an, FMT);
             const double ex = e.x, ey = e.y;
             const double2 p = P_l[r];
             kx = fma(ex, p.x, fma(ey, p.y, kx));
@@ -272,6 +276,15 @@ __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t
     }
   }
   __syncthreads();
+}
+
+// Format dispatch: the E-field format is a compile-time constant of the
+// inner loops.
+template <int J, int PS>
+__device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t* smem) {
+  if (a.fmt == kCI4) solve_channel_fmt<J, PS, kCI4>(a, f, smem);
+  else if (a.fmt == kCI8) solve_channel_fmt<J, PS, kCI8>(a, f, smem);
+  else solve_channel_fmt<J, PS, kCF32>(a, f, smem);
 }
 
 }  // namespace epic

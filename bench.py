@@ -50,8 +50,8 @@ PEAK_HBM_GBS = 8000.0
 # to those files makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "engine.h", "fft_reg.h", "epic_internal.h", "epic_api.hip")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "fe6ad469aaafb7ebd33308c5423e77e706396bb934be2c334bef7b68d2e8308f",
-            "fetch_kib": 174255.0, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "bb567ff9d0024b521b909f30a63b48c31f6c444cd93c29e12b4443b200078ade",
+            "fetch_kib": 177014.0, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
 }
 
 

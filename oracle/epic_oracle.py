@@ -240,6 +240,33 @@ def gain_update(Kbar, Qbar, A, D, g, na, gamma, flags=None, d_tiny=1e-12):
     return np.where(held, g, g_new), held
 
 
+def gain_update_multi(Kbar, Qbar, A, D, g, na, gamma, flags=None, d_tiny=1e-12):
+    """EPICal update from several tapped pixels (the multiple-pixel extension
+    named in Sec. 6; the paper gives no formula, this is the reading used).
+
+    Each pixel p gives its own autocorrelation-subtracted correlation
+      C_ap = K_ap - conj(A_ap) <|E_a|^2> / (Na conj(g_a))        (eq. Cna per pixel)
+    whose expectation is g_a D_ap / Na (eq. cal_solution per pixel).  The gain
+    is the least-squares solution over the pixels of Na C_ap = g_a D_ap,
+      g_a = Na sum_p conj(D_ap) C_ap / sum_p |D_ap|^2,
+    damped as in eq. (damping).  With one pixel this is Na C_a / D_a.
+    Kbar, A, D: [n_pix, Na].  Antennas that are flagged, whose
+    sum_p |D_ap|^2 is below d_tiny^2 times its largest value, or whose update
+    is not finite keep g_a.  Returns (g_new, held_mask).
+    """
+    Kbar, A, D = np.atleast_2d(Kbar), np.atleast_2d(A), np.atleast_2d(D)
+    C = Kbar - np.conj(A) * Qbar[None, :] / (na * np.conj(g))[None, :]
+    num = np.sum(np.conj(D) * C, axis=0)
+    den = np.sum(np.abs(D) ** 2, axis=0)
+    with np.errstate(all="ignore"):
+        g_new = (1.0 - gamma) * na * num / den + gamma * g
+    dmax = np.max(den) if den.size else 0.0
+    held = (den <= d_tiny * d_tiny * dmax) | ~np.isfinite(g_new)
+    if flags is not None:
+        held |= np.asarray(flags) != 0
+    return np.where(held, g, g_new), held
+
+
 # --------------------------------------------------------------------------
 # The whole loop (Fig. schematic; Sec. 2.2 feedback schedule)
 # --------------------------------------------------------------------------
@@ -261,6 +288,7 @@ class Problem:
     gamma: float
     t_cal: int
     flags: Optional[np.ndarray] = None
+    pix_lm: Optional[np.ndarray] = None   # [n_pix, 2] tapped directions (None: the calibrator only)
 
     @staticmethod
     def from_workload(wl) -> "Problem":
@@ -282,6 +310,21 @@ def channel_setup(pb: Problem, ch: int):
     flags = np.zeros(pb.ant_xy.shape[0], np.uint8) if pb.flags is None else np.asarray(pb.flags)
     na = float(np.sum(flags == 0))
     return dict(cells=cells, k0=k0, A=A, V=V, D=D, na=na, flags=flags)
+
+
+def pixel_setup(pb: Problem, ch: int, s=None):
+    """Per-channel tables of every tapped pixel: k_p, A_p, D_p ([n_pix, ...])."""
+    s = channel_setup(pb, ch) if s is None else s
+    lms = np.atleast_2d(pb.cal_lm if pb.pix_lm is None else pb.pix_lm)
+    f = float(pb.freq_hz[ch])
+    ks, As, Ds = [], [], []
+    for l, m in lms:
+        k = pixel_of_direction(l, m, f, pb.nx, pb.ny, pb.dx, pb.dy)
+        A = pixel_response(s["cells"], k[0], k[1], pb.nx, pb.ny)
+        ks.append(k)
+        As.append(A)
+        Ds.append(denominator(A, s["V"], pb.flags))
+    return dict(s, k=np.array(ks), A_p=np.array(As), D_p=np.array(Ds))
 
 
 def intervals(n_samples: int, t_cal: int):
@@ -325,6 +368,36 @@ def run_channel(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, setup=None,
     if keep_taps:
         out["taps"] = taps
     return out
+
+
+def run_channel_multi(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, setup=None):
+    """The calibrated loop with several tapped pixels (gain_update_multi).
+
+    Identical to run_channel except that every pixel p of pb.pix_lm is tapped,
+    P_p(t) = script-E'(s_p, t), correlated with the uncalibrated E-fields, and
+    the update combines the pixels.  Returns dict(image, gains, held).
+    """
+    s = pixel_setup(pb, ch) if setup is None else setup
+    cells, ks, A, D, na, flags = s["cells"], s["k"], s["A_p"], s["D_p"], s["na"], s["flags"]
+    T = E.shape[0]
+    g = np.array(g0, np.complex128).copy()
+    I = np.zeros((pb.ny, pb.nx), np.float64)
+    hist = [g.copy()]
+    held_hist = []
+    for (t0, t1) in intervals(T, pb.t_cal):
+        Ec = calibrate(E[t0:t1], g, flags)
+        X = dft2(grid(Ec, cells, pb.nx, pb.ny), na)
+        I += (np.abs(X) ** 2).sum(axis=0)
+        Eu = np.where(flags == 0, E[t0:t1], 0.0)
+        nt = t1 - t0
+        Ks = []
+        for (kx, ky) in ks:
+            K, Q = correlate(Eu, X[:, ky, kx])
+            Ks.append(K / nt)
+        g, held = gain_update_multi(np.array(Ks), Q / nt, A, D, g, na, pb.gamma, flags)
+        hist.append(g.copy())
+        held_hist.append(held)
+    return dict(image=I / T, gains=np.array(hist), held=np.array(held_hist))
 
 
 def run(E: np.ndarray, pb: Problem, g0: np.ndarray, channels=None):

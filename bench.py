@@ -142,17 +142,20 @@ def gain_rel_err(got, ref):
     return float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
 
 
-def cpu_baseline(wl, packed, budget_s, gpu_image=None, gpu_gains=None, extra_images=None):
+def cpu_baseline(wl, packed, budget_s, gpu_image=None, gpu_gains=None, extra_images=None, pix=None):
     """The FP64 oracle on whole channels of the same workload until the time
     budget is spent (at least one channel)."""
     from oracle import epic_oracle as O
     pb = O.Problem.from_workload(wl)
+    if pix is not None:
+        pb.pix_lm = pix
     done, results = [], []
     ch, t_used = 0, 0.0
     t0 = time.perf_counter()
     while ch < wl.array.n_chan and (not done or t_used < budget_s):
         E = O.unpack(packed[:, ch], wl.array.efmt)
-        results.append((ch, O.run_channel(E, pb, ch, wl.g0[ch])))
+        run = O.run_channel if pix is None else O.run_channel_multi
+        results.append((ch, run(E, pb, ch, wl.g0[ch])))
         done.append(ch)
         t_used = time.perf_counter() - t0
         ch += max(1, wl.array.n_chan // 7)
@@ -234,11 +237,16 @@ def copy_reference(dev):
     print("# copy reference: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
 
 
-def new_plan(specs_wls, opts=None):
+def new_plan(specs_wls, opts=None, pix=None):
+    """A plan over the arrays of `specs_wls`; with `pix` the first array's
+    EPICal taps those pixels instead of its calibrator alone."""
     from paper_1603_02126_amd import lib
     plan = lib.Plan([w.array for w in specs_wls])
     for i, w in enumerate(specs_wls):
-        plan.set_model(i, w.model_lmS, w.cal_lm, w.gamma, w.t_cal)
+        if i == 0 and pix is not None:
+            plan.set_model_pixels(i, w.model_lmS, pix, w.gamma, w.t_cal)
+        else:
+            plan.set_model(i, w.model_lmS, w.cal_lm, w.gamma, w.t_cal)
     for k, v in (opts or {}).items():
         plan.set_option(k, v)
     return plan
@@ -256,7 +264,12 @@ def bench_single(args, dev):
     print(f"# generated {packed.nbytes / 1e6:.1f} MB in {time.perf_counter() - tg:.1f} s", file=sys.stderr,
           flush=True)
 
-    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None)
+    pix = None
+    if args.pixels > 1:
+        # several tapped pixels: the brightest model sources (the calibrator first)
+        order = np.argsort(-wl.model_lmS[:, 2], kind="stable")[:args.pixels]
+        pix = wl.model_lmS[order, :2]
+    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None, pix)
     e = torch.from_numpy(packed).to(dev)
     g0 = torch.from_numpy(wl.g0).to(dev)
     g = torch.empty_like(g0)
@@ -276,7 +289,7 @@ def bench_single(args, dev):
     if not args.no_forms:
         if a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512):
             # form 1: split-precision DFT-GEMM on the matrix cores, same workload
-            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2})
+            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2}, pix)
             img_d = torch.zeros_like(img)
             dt_d, tim_d = Timer([plan_d])(stepper(plan_d, img_d), args.steps, args.warmup)
             ms_img_d = tim_d[lib.TIMER_IMAGE][0] / max(1, tim_d[lib.TIMER_IMAGE][1])
@@ -293,7 +306,7 @@ def bench_single(args, dev):
             forms["dft_gemm_fp16_split"] = {"supported": False,
                                              "reason": "the DFT-GEMM form covers arrays of at most 512 antennas"}
         # form 2: batched launches captured in a hipGraph, after autotuning
-        plan_g = new_plan([wl])
+        plan_g = new_plan([wl], None, pix)
         tuning = plan_g.autotune([e], wl.n_samples)
         plan_g.set_option(lib.OPT_BATCH, 1)
         plan_g.set_option(lib.OPT_GRAPH, 1)
@@ -328,7 +341,7 @@ def bench_single(args, dev):
     if args.cpu_budget > 0:
         print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         extra = {k: v["_image"].cpu().numpy() for k, v in forms.items() if "_image" in v}
-        cpu, parity = cpu_baseline(wl, packed, args.cpu_budget, img.cpu().numpy(), gains_plain, extra)
+        cpu, parity = cpu_baseline(wl, packed, args.cpu_budget, img.cpu().numpy(), gains_plain, extra, pix)
     for v in forms.values():
         v.pop("_image", None)
 
@@ -337,7 +350,7 @@ def bench_single(args, dev):
     out = base_record(args, value, ms_step, "f32", {
         "workload": describe(wl), "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan,
         "grid": [a.ny, a.nx], "n_samples": wl.n_samples, "t_cal": wl.t_cal, "efmt": synth.FMT_NAMES[a.efmt],
-        "path": "plain FP32 FFT", "parallelism": "1 GPU"})
+        "path": "plain FP32 FFT", "parallelism": "1 GPU", "tapped_pixels": args.pixels})
     out.update({
         "msamples_per_s": value * a.n_ant / 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -549,6 +562,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
+    ap.add_argument("--pixels", type=int, default=1,
+                    help="tapped pixels of EPICal (lwa/hera/tiny; > 1: calibrator plus brightest sources)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

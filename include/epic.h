@@ -125,6 +125,12 @@ int epic_host_grid_cells(const epic_array_desc* desc, int32_t* ixy, double* w);
 int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* model,
                          int32_t* k0, double* A, double* D);
 
+/* The same tables for several tapped pixels (see epical_set_model_pixels):
+ * k0 host [n_pix][F][2], A and D host [n_pix][F][Na] complex128; any may be
+ * NULL. */
+int epic_host_calibrator_pixels(const epic_array_desc* desc, const epic_model_desc* model, const double* pix_lm,
+                                int32_t n_pix, int32_t* k0, double* A, double* D);
+
 /* ---------------------------------------------------------------------- */
 /* Plans                                                                   */
 /* ---------------------------------------------------------------------- */
@@ -140,6 +146,29 @@ int epic_plan_destroy(epic_plan_t plan);
 /* Set the calibration model of one array (required before epical_update and
  * epic_run): computes k0, A and D on the host and uploads them. */
 int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* model);
+
+/* EPICal from several tapped pixels (the multiple-pixel correlations named
+ * in Sec. 6; the paper gives no formula, the reading used is stated here).
+ * Like epical_set_model, with the tapped directions given explicitly (the
+ * model's cal_l, cal_m are not used).
+ *   pix_lm: host [n_pix][2] direction cosines (l, m), 1 <= n_pix <=
+ *           EPIC_MAX_PIX; copied.  Pixel 0 is the one epic_image_accumulate
+ *           reports as the tap.
+ * Each pixel p has its own k_p, A_ap and D_ap (as epic_host_calibrator
+ * computes them for one direction); epic_run taps every pixel,
+ * P_p(t) = script-E'(s_p, t), correlates it with the uncalibrated E-fields,
+ * C_ap = <E_a P_p*> - conj(A_ap) <|E_a|^2> / (Na conj g_a) (eq. Cna per
+ * pixel), and updates each gain with the least-squares solution over the
+ * pixels of Na C_ap = g_a D_ap (eq. cal_solution per pixel), damped as in
+ * eq. (damping):
+ *   g_a <- (1 - gamma) Na sum_p conj(D_ap) C_ap / sum_p |D_ap|^2 + gamma g_a.
+ * With one pixel this is epical_set_model's update.  An antenna whose
+ * sum_p |D_ap|^2 is below 1e-24 of the largest is held.  Needs Na <= 1024
+ * when n_pix > 1 (EPIC_ERR_UNSUPPORTED otherwise); epical_update (one tap
+ * per sample) then returns EPIC_ERR_UNSUPPORTED. */
+#define EPIC_MAX_PIX 4
+int epical_set_model_pixels(epic_plan_t plan, int32_t array, const epic_model_desc* model, const double* pix_lm,
+                            int32_t n_pix);
 
 /* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)

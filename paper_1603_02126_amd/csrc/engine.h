@@ -205,6 +205,39 @@ __device__ __forceinline__ double2 epical_step(double2 Kbar, double Qbar, double
 }
 
 
+// Update from several tapped pixels: the least-squares combination over the
+// pixels of Na C_ap = g_a D_ap (C_ap as in epical_step, per pixel), damped.
+__device__ __forceinline__ double2 epical_step_multi(const double2 (&Kbar)[kMaxPix], double Qbar,
+                                                     const double2 (&A)[kMaxPix], const double2 (&D)[kMaxPix],
+                                                     int np, double2 g, uint8_t hold, double na, double gamma,
+                                                     uint32_t* st) {
+  if (hold) {
+    *st |= (hold & kHoldFlagged ? 1u : 0u) | (hold & kHoldDZero ? 2u : 0u);
+    return g;
+  }
+  const double2 inv = zdiv(make_double2(1.0, 0.0), make_double2(na * g.x, -na * g.y));   // 1 / (Na conj g)
+  double2 num = make_double2(0.0, 0.0);
+  double den = 0.0;
+#pragma unroll
+  for (int p = 0; p < kMaxPix; ++p) {
+    if (p < np) {
+      const double2 t = zmul(make_double2(A[p].x * Qbar, -A[p].y * Qbar), inv);
+      const double2 C = make_double2(Kbar[p].x - t.x, Kbar[p].y - t.y);
+      const double2 dc = zmul(zconj(D[p]), C);
+      num.x += dc.x;
+      num.y += dc.y;
+      den += D[p].x * D[p].x + D[p].y * D[p].y;
+    }
+  }
+  const double2 sol = make_double2(na * num.x / den, na * num.y / den);
+  const double2 gn = make_double2((1.0 - gamma) * sol.x + gamma * g.x, (1.0 - gamma) * sol.y + gamma * g.y);
+  if (!isfinite(gn.x) || !isfinite(gn.y)) {
+    *st |= 4u;
+    return g;
+  }
+  return gn;
+}
+
 template <int N, int K2, int APL>
 struct DegridTable {
   int off[APL][K2];

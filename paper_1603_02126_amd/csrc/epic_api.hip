@@ -121,10 +121,18 @@ void grid_cells(const HostArray& h, std::vector<int32_t>& ix, std::vector<int32_
 }
 
 struct ModelTables {
-  std::vector<int32_t> k0;   // [F][2]
-  std::vector<zc> A, D;      // [F][Na]
+  std::vector<int32_t> k0;   // [n_pix][F][2]
+  std::vector<zc> A, D;      // [n_pix][F][Na]
   std::vector<uint8_t> hold; // [F][Na]
 };
+
+static int check_pixels(const double* pix_lm, int n_pix) {
+  if (!pix_lm) return fail(EPIC_ERR_ARG, "pixel directions are NULL");
+  if (n_pix < 1 || n_pix > EPIC_MAX_PIX) return fail(EPIC_ERR_ARG, "n_pix must be in 1..%d (got %d)", EPIC_MAX_PIX, n_pix);
+  for (int i = 0; i < 2 * n_pix; ++i)
+    if (!std::isfinite(pix_lm[i])) return fail(EPIC_ERR_ARG, "pixel direction not finite");
+  return EPIC_OK;
+}
 
 int check_model(const epic_model_desc* m) {
   if (!m) return fail(EPIC_ERR_ARG, "model descriptor is NULL");
@@ -143,59 +151,67 @@ int check_model(const epic_model_desc* m) {
 //   V^M_ab = sum_s S_s e_a(s) conj(e_b(s)),  e_a(s) = exp(-2 pi i f r_a . s / c)
 // factored as D_a = sum_s S_s e_a(s) B(s) - [a unflagged] conj(A_a) sum_s S_s
 // with B(s) = sum_{b unflagged} conj(A_b) conj(e_b(s)).
-void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t) {
+// Tapped pixels: pix_lm [n_pix][2] or, when null, the model's calibrator.
+void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t, const double* pix_lm = nullptr,
+                  int n_pix = 1) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
-  t.k0.assign(2 * size_t(h.F), 0);
-  t.A.assign(size_t(h.F) * h.na, zc(0, 0));
-  t.D.assign(size_t(h.F) * h.na, zc(0, 0));
-  t.hold.assign(size_t(h.F) * h.na, 0);
+  const size_t FN = size_t(h.F) * h.na;
+  t.k0.assign(2 * size_t(h.F) * n_pix, 0);
+  t.A.assign(FN * n_pix, zc(0, 0));
+  t.D.assign(FN * n_pix, zc(0, 0));
+  t.hold.assign(FN, 0);
   const int ns = m->n_src;
   double Stot = 0;
   for (int s = 0; s < ns; ++s) Stot += m->src_lmS[3 * s + 2];
   std::vector<zc> e(size_t(h.na) * ns);
+  std::vector<double> den(h.na);
   for (int f = 0; f < h.F; ++f) {
     const double fr = h.freq[f];
-    const long long kxs = (long long)std::floor(m->cal_l * fr * h.nx * h.dx / kC + 0.5);
-    const long long kys = (long long)std::floor(m->cal_m * fr * h.ny * h.dy / kC + 0.5);
-    const long long kx = ((kxs % h.nx) + h.nx) % h.nx, ky = ((kys % h.ny) + h.ny) % h.ny;
-    t.k0[2 * f] = int32_t(kx);
-    t.k0[2 * f + 1] = int32_t(ky);
-    zc* A = &t.A[size_t(f) * h.na];
-    for (int a = 0; a < h.na; ++a) {
-      zc s(0, 0);
-      for (int k = 0; k < h.k2; ++k) {
-        const size_t q = size_t(a) * h.k2 + k;
-        const double ph = kTwoPi * (double((ix[q] * kx) % h.nx) / h.nx + double((iy[q] * ky) % h.ny) / h.ny);
-        s += w[q] * zc(std::cos(ph), std::sin(ph));
-      }
-      A[a] = s;
-    }
     for (int a = 0; a < h.na; ++a)
       for (int s = 0; s < ns; ++s) {
         const double l = m->src_lmS[3 * s], mm = m->src_lmS[3 * s + 1];
         const double ph = -kTwoPi * fr * (h.xy[2 * a] * l + h.xy[2 * a + 1] * mm) / kC;
         e[size_t(a) * ns + s] = zc(std::cos(ph), std::sin(ph));
       }
-    std::vector<zc> B(ns, zc(0, 0));
-    for (int b = 0; b < h.na; ++b) {
-      if (h.flag[b]) continue;
-      for (int s = 0; s < ns; ++s) B[s] += std::conj(A[b]) * std::conj(e[size_t(b) * ns + s]);
+    std::fill(den.begin(), den.end(), 0.0);
+    for (int p = 0; p < n_pix; ++p) {
+      const double pl = pix_lm ? pix_lm[2 * p] : m->cal_l, pm = pix_lm ? pix_lm[2 * p + 1] : m->cal_m;
+      const long long kxs = (long long)std::floor(pl * fr * h.nx * h.dx / kC + 0.5);
+      const long long kys = (long long)std::floor(pm * fr * h.ny * h.dy / kC + 0.5);
+      const long long kx = ((kxs % h.nx) + h.nx) % h.nx, ky = ((kys % h.ny) + h.ny) % h.ny;
+      t.k0[2 * (size_t(p) * h.F + f)] = int32_t(kx);
+      t.k0[2 * (size_t(p) * h.F + f) + 1] = int32_t(ky);
+      zc* A = &t.A[size_t(p) * FN + size_t(f) * h.na];
+      for (int a = 0; a < h.na; ++a) {
+        zc s(0, 0);
+        for (int k = 0; k < h.k2; ++k) {
+          const size_t q = size_t(a) * h.k2 + k;
+          const double ph = kTwoPi * (double((ix[q] * kx) % h.nx) / h.nx + double((iy[q] * ky) % h.ny) / h.ny);
+          s += w[q] * zc(std::cos(ph), std::sin(ph));
+        }
+        A[a] = s;
+      }
+      std::vector<zc> B(ns, zc(0, 0));
+      for (int b = 0; b < h.na; ++b) {
+        if (h.flag[b]) continue;
+        for (int s = 0; s < ns; ++s) B[s] += std::conj(A[b]) * std::conj(e[size_t(b) * ns + s]);
+      }
+      zc* D = &t.D[size_t(p) * FN + size_t(f) * h.na];
+      for (int a = 0; a < h.na; ++a) {
+        zc acc(0, 0);
+        for (int s = 0; s < ns; ++s) acc += m->src_lmS[3 * s + 2] * e[size_t(a) * ns + s] * B[s];
+        if (!h.flag[a]) acc -= std::conj(A[a]) * Stot;
+        D[a] = acc;
+        den[a] += std::norm(acc);
+      }
     }
-    zc* D = &t.D[size_t(f) * h.na];
-    double dmax = 0;
-    for (int a = 0; a < h.na; ++a) {
-      zc acc(0, 0);
-      for (int s = 0; s < ns; ++s) acc += m->src_lmS[3 * s + 2] * e[size_t(a) * ns + s] * B[s];
-      if (!h.flag[a]) acc -= std::conj(A[a]) * Stot;
-      D[a] = acc;
-      dmax = std::max(dmax, std::abs(acc));
-    }
+    const double dmax = *std::max_element(den.begin(), den.end());
     for (int a = 0; a < h.na; ++a) {
       uint8_t hb = 0;
       if (h.flag[a]) hb |= epic::kHoldFlagged;
-      if (!(std::abs(D[a]) > 1e-12 * dmax)) hb |= epic::kHoldDZero;
+      if (!(den[a] > 1e-24 * dmax)) hb |= epic::kHoldDZero;   // sum_p |D_ap|^2 vs (1e-12 max)^2
       t.hold[size_t(f) * h.na + a] = hb;
     }
   }
@@ -346,10 +362,11 @@ struct ArrayPlan {
   bool has_model = false;
   double gamma = 0;
   int t_cal = 1;
-  int32_t* d_k0 = nullptr;
-  double2* d_A = nullptr;
-  double2* d_D = nullptr;
+  int32_t* d_k0 = nullptr;     // [n_pix][F][2]
+  double2* d_A = nullptr;      // [n_pix][F][Na]
+  double2* d_D = nullptr;      // [n_pix][F][Na]
   uint8_t* d_hold = nullptr;
+  int n_pix = 1;
 };
 
 struct TimerRec {
@@ -534,6 +551,23 @@ int epic_host_grid_cells(const epic_array_desc* desc, int32_t* ixy, double* w) {
   return EPIC_OK;
 }
 
+int epic_host_calibrator_pixels(const epic_array_desc* desc, const epic_model_desc* model, const double* pix_lm,
+                                int32_t n_pix, int32_t* k0, double* A, double* D) {
+  HostArray h;
+  int rc = check_desc(desc, &h);
+  if (rc) return rc;
+  rc = check_model(model);
+  if (rc) return rc;
+  rc = check_pixels(pix_lm, n_pix);
+  if (rc) return rc;
+  ModelTables t;
+  model_tables(h, model, t, pix_lm, n_pix);
+  if (k0) std::memcpy(k0, t.k0.data(), t.k0.size() * sizeof(int32_t));
+  if (A) std::memcpy(A, t.A.data(), t.A.size() * sizeof(zc));
+  if (D) std::memcpy(D, t.D.data(), t.D.size() * sizeof(zc));
+  return EPIC_OK;
+}
+
 int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* model, int32_t* k0, double* A,
                          double* D) {
   HostArray h;
@@ -644,15 +678,32 @@ int epic_plan_destroy(epic_plan_t plan) {
   return EPIC_OK;
 }
 
+static int set_model_tables(epic_plan_t plan, int32_t array, const epic_model_desc* model, const double* pix_lm,
+                            int n_pix);
+
 int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* model) {
+  return set_model_tables(plan, array, model, nullptr, 1);
+}
+
+int epical_set_model_pixels(epic_plan_t plan, int32_t array, const epic_model_desc* model, const double* pix_lm,
+                            int32_t n_pix) {
+  int rc = check_pixels(pix_lm, n_pix);
+  if (rc) return rc;
+  return set_model_tables(plan, array, model, pix_lm, n_pix);
+}
+
+static int set_model_tables(epic_plan_t plan, int32_t array, const epic_model_desc* model, const double* pix_lm,
+                            int n_pix) {
   int rc = check_plan(plan, array);
   if (rc) return rc;
   rc = check_model(model);
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
   if (ap.h.na_eff < 2) return fail(EPIC_ERR_ARG, "calibration needs at least two unflagged antennas");
+  if (n_pix > 1 && !epic::solve_supported(ap.h.na, ap.h.efmt, n_pix))
+    return fail(EPIC_ERR_UNSUPPORTED, "several tapped pixels need Na <= 1024 (got %d)", ap.h.na);
   ModelTables t;
-  model_tables(ap.h, model, t);
+  model_tables(ap.h, model, t, pix_lm, n_pix);
   hipFree(ap.d_k0);
   hipFree(ap.d_A);
   hipFree(ap.d_D);
@@ -668,6 +719,7 @@ int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* mod
   if (rc) return rc;
   ap.gamma = model->gamma;
   ap.t_cal = model->t_cal;
+  ap.n_pix = n_pix;
   ap.has_model = true;
   plan->generation++;
   return EPIC_OK;
@@ -759,6 +811,9 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
   if (rc) return rc;
   ArrayPlan& ap = plan->arrays[array];
   if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", array);
+  if (ap.n_pix != 1)
+    return fail(EPIC_ERR_UNSUPPORTED, "the stage-wise update takes one tap per sample; this array has %d pixels "
+                "(use epic_run)", ap.n_pix);
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (!kq || !gains) return fail(EPIC_ERR_ARG, "kq and gains must not be NULL");
   if (nt > 0 && (!efield || !tap)) return fail(EPIC_ERR_ARG, "efield and tap must not be NULL");
@@ -880,6 +935,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
                             gain_hist ? reinterpret_cast<double2*>(gain_hist[i])
                                       : reinterpret_cast<double2*>(scr + lay[i].gh_off),
                             ant_status ? ant_status[i] : nullptr};
+    sa[i].n_pix = ap.n_pix;
   }
   // FP32 u of every interval from the gain history the solve wrote
   auto hist_to_u = [&](int i) -> hipError_t {
@@ -986,7 +1042,7 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     ArrayPlan& ap = plan->arrays[i];
     if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", i);
     if ((rc = check_grid_supported(ap))) return rc;
-    if (!epic::solve_supported(ap.h.na, ap.h.efmt))
+    if (!epic::solve_supported(ap.h.na, ap.h.efmt, ap.n_pix))
       return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
     lay[i].n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;

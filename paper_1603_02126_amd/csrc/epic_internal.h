@@ -62,15 +62,17 @@ struct SolveArgs {
   int F, Na, fmt;
   int64_t t_cal;
   int n_int;
-  const double2* A;         // [F][Na]
-  const double2* D;         // [F][Na]
+  const double2* A;         // [n_pix][F][Na]
+  const double2* D;         // [n_pix][F][Na]
   const uint8_t* hold;      // [F][Na] kHold* bits
   double na_eff, gamma;
   double2* gains;           // [F][Na] in/out
   float2* u_hist;           // [n_int][F][Na] (written by launch_hist_to_u from g_hist)
   double2* g_hist;          // [n_int+1][F][Na], required
   uint32_t* status;         // [F][Na] or null
+  int n_pix = 1;            // tapped pixels (1..kMaxPix; > 1 needs Na <= kSolveThreads)
 };
+constexpr int kMaxPix = 4;
 
 // Stage-wise EPICal accumulate / finalize.
 struct UpdateArgs {
@@ -159,7 +161,7 @@ hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);
 hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
                          float* image, hipStream_t s);
-bool solve_supported(int na, int fmt);
+bool solve_supported(int na, int fmt, int n_pix = 1);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 // u_hist[n] = 1 / g_hist[n] (FP64, rounded to FP32; zero for flagged antennas), n < n_int
 hipError_t launch_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_int, int F, int Na, float2* u_hist,

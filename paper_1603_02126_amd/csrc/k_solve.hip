@@ -59,9 +59,10 @@ static int stage_cap(int RB) {
   return RB % 16 == 0 ? Stager<16, MAXP>::CAP : RB % 4 == 0 ? Stager<4, MAXP>::CAP : Stager<1, MAXP>::CAP;
 }
 
-bool solve_supported(int na, int fmt) {
+bool solve_supported(int na, int fmt, int n_pix) {
   const int RB = na * efmt_bytes(fmt);
   const int cap = na <= kSolveThreads ? stage_cap<8>(RB) : stage_cap<4>(RB);   // the stagers of J = 1 and 2
+  if (n_pix < 1 || n_pix > kMaxPix || (n_pix > 1 && na > kSolveThreads)) return false;
   return na >= 1 && na <= 2 * kSolveThreads && RB <= cap;
 }
 
@@ -75,7 +76,7 @@ static hipError_t launch_solve_j(const SolveArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
-  if (!solve_supported(a.Na, a.fmt)) return hipErrorInvalidValue;
+  if (!solve_supported(a.Na, a.fmt, a.n_pix)) return hipErrorInvalidValue;
   if (a.Na <= kSolveThreads) return launch_solve_j<1>(a, s);
   return launch_solve_j<2>(a, s);
 }

@@ -103,10 +103,14 @@ __device__ __forceinline__ double row16_sum_lane15(double x) {
 // J = antennas per thread slot (Na <= 1024 * J), PS = chunk piece size.
 // LDS of one solve workgroup: two chunk buffers, the taps of a chunk and the
 // coefficients c_a (up to 2 * kSolveThreads antennas), both FP64.
+// With several tapped pixels the same areas hold the taps [kMaxPix][256]
+// and the coefficients [kMaxPix][kSolveThreads].
+constexpr int kSolveMultiRows = kSolveMaxRows / kMaxPix;
 struct SolveSmem {
   static constexpr int P_OFF = 2 * kSolveChunkBytes;
   static constexpr int C_OFF = P_OFF + kSolveMaxRows * 16;
-  static constexpr int BYTES = C_OFF + 2 * kSolveThreads * 16;
+  static constexpr int BYTES = C_OFF + kMaxPix * kSolveThreads * 16;
+  static_assert(2 * kSolveThreads <= kMaxPix * kSolveThreads, "coefficients of 2048 antennas fit");
 };
 
 template <int J, int PS, int FMT>
@@ -278,10 +282,180 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// EPICal from several tapped pixels (the multiple-pixel extension of Sec. 6):
+// per interval the taps P_p(t) = sum_a c_pa E_a(t) of every pixel, the
+// correlations K_ap = <E_a P_p*>, and the least-squares update over the
+// pixels (epical_step_multi).  Na <= kSolveThreads, at most kMaxPix pixels;
+// the loops over pixels are unrolled to kMaxPix with guards.
+// ---------------------------------------------------------------------------
+template <int PS, int FMT>
+__device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, uint8_t* smem) {
+  uint8_t (*chunk)[kSolveChunkBytes] = reinterpret_cast<uint8_t (*)[kSolveChunkBytes]>(smem);
+  double2* P_l = reinterpret_cast<double2*>(smem + SolveSmem::P_OFF);   // [kMaxPix][kSolveMultiRows]
+  double2* c_l = reinterpret_cast<double2*>(smem + SolveSmem::C_OFF);   // [kMaxPix][kSolveThreads]
+  const int tid = threadIdx.x;
+  const int np = a.n_pix;
+  constexpr int bpe = FMT == kCF32 ? 8 : FMT == kCI8 ? 2 : 1;
+  const int RB = a.Na * bpe;
+  const int64_t rowstride = int64_t(a.F) * RB;
+  const int64_t pstride = int64_t(a.F) * a.Na;
+  const uint8_t* ebase = a.efield + int64_t(f) * RB;
+  using Stage = Stager<PS, 8>;
+  int rpc = Stage::CAP / RB;
+  rpc = rpc < kSolveMultiRows ? rpc : kSolveMultiRows;
+
+  int NaP = 16;
+  while (NaP < a.Na && NaP < kSolveThreads) NaP <<= 1;
+  const int RG = kSolveThreads / NaP;
+  const int rg = tid % RG;
+  const int an = tid / RG;
+  const bool own = an < a.Na;
+  const int64_t ia = int64_t(f) * a.Na + (own ? an : 0);
+
+  double2 g = make_double2(0.0, 0.0), A[kMaxPix], D[kMaxPix];
+  uint8_t hold = 0;
+  uint32_t st = 0u;
+#pragma unroll
+  for (int p = 0; p < kMaxPix; ++p) {
+    A[p] = D[p] = make_double2(0.0, 0.0);
+    if (own && p < np) {
+      A[p] = a.A[p * pstride + ia];
+      D[p] = a.D[p * pstride + ia];
+    }
+  }
+  if (own) {
+    g = a.gains[ia];
+    hold = a.hold[ia];
+    if (rg == 0) a.g_hist[ia] = g;
+  }
+
+  auto interval_len = [&](int n) -> int {
+    const int64_t t0 = int64_t(n) * a.t_cal;
+    return int(min(a.t_cal, a.n_t - t0));
+  };
+  Stage stg;
+  int cur_buf = 0;
+  {
+    const int nr = min(rpc, interval_len(0));
+    stg.load(ebase, rowstride, 0, nr, RB, tid);
+    stg.store(chunk[0], nr, RB, tid);
+  }
+  __syncthreads();
+
+  for (int n = 0; n < a.n_int; ++n) {
+    const int len = interval_len(n);
+    if (rg == 0 && own) {
+      double2 u = zrecip(g);
+      if (hold & kHoldFlagged) u = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int p = 0; p < kMaxPix; ++p)
+        if (p < np) {
+          const double2 c = zmul(A[p], u);
+          c_l[p * kSolveThreads + an] = make_double2(c.x / a.na_eff, c.y / a.na_eff);
+        }
+    }
+    double Kx[kMaxPix], Ky[kMaxPix], Q = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxPix; ++p) Kx[p] = Ky[p] = 0.0;
+    __syncthreads();
+    for (int r0 = 0; r0 < len; r0 += rpc) {
+      const int nr = min(rpc, len - r0);
+      int n_nx = n, r_nx = r0 + nr;
+      if (r_nx >= len) {
+        n_nx = n + 1;
+        r_nx = 0;
+      }
+      const bool have_next = n_nx < a.n_int;
+      const int nr_nx = have_next ? min(rpc, interval_len(n_nx) - r_nx) : 0;
+      if (have_next) stg.load(ebase, rowstride, int64_t(n_nx) * a.t_cal + r_nx, nr_nx, RB, tid);
+      const uint8_t* ch = chunk[cur_buf];
+      // taps of every pixel: 16 lanes per row, DPP sums within the 16-lane row
+      {
+        const int q = tid & 15, rr = tid >> 4;
+        for (int rb = 0; rb < nr; rb += kSolveThreads / 16) {
+          const int r = rb + rr;
+          double px[kMaxPix], py[kMaxPix];
+#pragma unroll
+          for (int p = 0; p < kMaxPix; ++p) px[p] = py[p] = 0.0;
+          if (r < nr) {
+            const uint8_t* row = ch + r * RB;
+            for (int k = q; k < a.Na; k += 16) {
+              const float2 e = load_sample(row, k, FMT);
+              const double ex = e.x, ey = e.y;
+#pragma unroll
+              for (int p = 0; p < kMaxPix; ++p)
+                if (p < np) {
+                  const double2 c = c_l[p * kSolveThreads + k];
+                  px[p] = fma(c.x, ex, fma(-c.y, ey, px[p]));
+                  py[p] = fma(c.x, ey, fma(c.y, ex, py[p]));
+                }
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < kMaxPix; ++p)
+            if (p < np) {
+              const double sx = row16_sum_lane15(px[p]), sy = row16_sum_lane15(py[p]);
+              if (q == 15 && r < nr) P_l[p * kSolveMultiRows + r] = make_double2(sx, sy);
+            }
+        }
+      }
+      __syncthreads();
+      if (own) {
+#pragma unroll 2
+        for (int r = rg; r < nr; r += RG) {
+          const float2 e = load_sample(ch + r * RB, an, FMT);
+          const double ex = e.x, ey = e.y;
+#pragma unroll
+          for (int p = 0; p < kMaxPix; ++p)
+            if (p < np) {
+              const double2 P = P_l[p * kSolveMultiRows + r];
+              Kx[p] = fma(ex, P.x, fma(ey, P.y, Kx[p]));
+              Ky[p] = fma(ey, P.x, fma(-ex, P.y, Ky[p]));
+            }
+          Q = fma(ex, ex, fma(ey, ey, Q));
+        }
+      }
+      if (have_next) stg.store(chunk[cur_buf ^ 1], nr_nx, RB, tid);
+      __syncthreads();
+      cur_buf ^= 1;
+    }
+    for (int m = 1; m < RG; m <<= 1) {
+#pragma unroll
+      for (int p = 0; p < kMaxPix; ++p) {
+        Kx[p] += __shfl_xor(Kx[p], m);
+        Ky[p] += __shfl_xor(Ky[p], m);
+      }
+      Q += __shfl_xor(Q, m);
+    }
+    if (own) {
+      const double inv_n = 1.0 / double(len);
+      double2 Kb[kMaxPix];
+#pragma unroll
+      for (int p = 0; p < kMaxPix; ++p) Kb[p] = make_double2(Kx[p] * inv_n, Ky[p] * inv_n);
+      g = epical_step_multi(Kb, Q * inv_n, A, D, np, g, hold, a.na_eff, a.gamma, &st);
+      if (rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = g;
+    }
+  }
+  if (rg == 0 && own) {
+    a.gains[ia] = g;
+    if (a.status) a.status[ia] |= st;
+  }
+  __syncthreads();
+}
+
 // Format dispatch: the E-field format is a compile-time constant of the
-// inner loops.
+// inner loops; several tapped pixels take the multi-pixel solve (J = 1).
 template <int J, int PS>
 __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t* smem) {
+  if constexpr (J == 1) {
+    if (a.n_pix > 1) {
+      if (a.fmt == kCI4) solve_channel_multi<PS, kCI4>(a, f, smem);
+      else if (a.fmt == kCI8) solve_channel_multi<PS, kCI8>(a, f, smem);
+      else solve_channel_multi<PS, kCF32>(a, f, smem);
+      return;
+    }
+  }
   if (a.fmt == kCI4) solve_channel_fmt<J, PS, kCI4>(a, f, smem);
   else if (a.fmt == kCI8) solve_channel_fmt<J, PS, kCI8>(a, f, smem);
   else solve_channel_fmt<J, PS, kCF32>(a, f, smem);

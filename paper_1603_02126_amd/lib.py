@@ -59,6 +59,11 @@ _SIGS = {
     "epic_plan_create": (ctypes.c_int, [ctypes.POINTER(ArrayDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "epic_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "epical_set_model": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ModelDesc)]),
+    "epical_set_model_pixels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ModelDesc),
+                                               ctypes.c_void_p, ctypes.c_int32]),
+    "epic_host_calibrator_pixels": (ctypes.c_int, [ctypes.POINTER(ArrayDesc), ctypes.POINTER(ModelDesc),
+                                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
     "epic_plan_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
     "epic_plan_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "epic_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -167,6 +172,20 @@ def host_calibrator(spec, model_lmS, cal_lm, gamma=0.5, t_cal=1):
     return k0, A, D
 
 
+def host_calibrator_pixels(spec, model_lmS, pix_lm, gamma=0.5, t_cal=1):
+    """(k [P, F, 2], A [P, F, Na], D [P, F, Na]) of several tapped pixels."""
+    d = _DescHolder(spec)
+    pix = np.ascontiguousarray(np.atleast_2d(pix_lm), np.float64)
+    m = _ModelHolder(model_lmS, pix[0], gamma, t_cal)
+    P, F, na = pix.shape[0], d.freq.shape[0], d.xy.shape[0]
+    k0 = np.zeros((P, F, 2), np.int32)
+    A = np.zeros((P, F, na), np.complex128)
+    D = np.zeros((P, F, na), np.complex128)
+    _check(load().epic_host_calibrator_pixels(ctypes.byref(d.desc), ctypes.byref(m.desc), pix.ctypes.data, P,
+                                              k0.ctypes.data, A.ctypes.data, D.ctypes.data))
+    return k0, A, D
+
+
 # --------------------------------------------------------------------------
 # device plan
 # --------------------------------------------------------------------------
@@ -247,6 +266,15 @@ class Plan:
     def set_model(self, array: int, model_lmS, cal_lm, gamma: float, t_cal: int):
         m = _ModelHolder(model_lmS, cal_lm, gamma, t_cal)
         _check(load().epical_set_model(self._h, int(array), ctypes.byref(m.desc)))
+        self._models[array] = m
+
+    def set_model_pixels(self, array: int, model_lmS, pix_lm, gamma: float, t_cal: int):
+        """epical_set_model_pixels: EPICal from several tapped directions pix_lm [P, 2]."""
+        pix = np.ascontiguousarray(np.atleast_2d(pix_lm), np.float64)
+        m = _ModelHolder(model_lmS, pix[0], gamma, t_cal)
+        _check(load().epical_set_model_pixels(self._h, int(array), ctypes.byref(m.desc), pix.ctypes.data,
+                                              int(pix.shape[0])))
+        m.pix = pix
         self._models[array] = m
 
     def set_option(self, key: int, value: int):

@@ -106,3 +106,39 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(lib, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         lib.load()
+
+
+def test_pixel_tables_match_oracle():
+    """Tables of several tapped pixels (k_p, A_p, D_p) against the oracle."""
+    wl = synth.config_small(n_chan=2)
+    flags = np.zeros(wl.array.n_ant, np.uint8)
+    flags[[2, 9]] = 1
+    arr = synth.dataclasses.replace(wl.array, ant_flag=flags)
+    wl = wl.replace(array=arr)
+    pix = wl.src_lmS[[0, 3, 6], :2]
+    k, A, D = lib.host_calibrator_pixels(arr, wl.model_lmS, pix, wl.gamma, wl.t_cal)
+    pb = O.Problem.from_workload(wl)
+    pb.pix_lm = pix
+    for f in range(arr.n_chan):
+        s = O.pixel_setup(pb, f)
+        np.testing.assert_array_equal(k[:, f], s["k"])
+        np.testing.assert_allclose(A[:, f], s["A_p"], rtol=0, atol=1e-13)
+        scale = np.abs(s["D_p"]).max()
+        np.testing.assert_allclose(D[:, f], s["D_p"], rtol=0, atol=1e-11 * scale)
+    # one pixel at the calibrator is the single-pixel table
+    k1, A1, D1 = lib.host_calibrator_pixels(arr, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
+    k0, A0, D0 = lib.host_calibrator(arr, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
+    np.testing.assert_array_equal(k1[0], k0)
+    np.testing.assert_array_equal(A1[0], A0)
+    np.testing.assert_array_equal(D1[0], D0)
+
+
+@pytest.mark.parametrize("n_pix", [0, 5])
+def test_pixel_count_errors(n_pix):
+    wl = synth.config_small(n_chan=1)
+    pix = np.zeros((max(n_pix, 1), 2))
+    with pytest.raises(lib.EpicError):
+        d = lib._DescHolder(wl.array)
+        m = lib._ModelHolder(wl.model_lmS, wl.cal_lm, 0.5, 10)
+        lib._check(lib.load().epic_host_calibrator_pixels(ctypes.byref(d.desc), ctypes.byref(m.desc),
+                                                          pix.ctypes.data, n_pix, None, None, None))

@@ -45,6 +45,13 @@ listed with its reason in the design notes of the repository):
 * The gain recursion follows eq. (damping) exactly, so the single-source
   limit of Sec. 2.2 comes out as (Na - 1) S_src in the denominator (the sum
   excludes b = a), not Na S_src.
+* Several tapped pixels (Sec. 6): the gain is the least-squares solution over
+  the pixels of Na C_ap = g_a D_ap, damped (gain_update_multi).
+* Gains shared over a band of channels (Sec. 5 averaging, Sec. 6 gain-model
+  fitting): the undamped per-channel solutions Na C/D of the band's channels
+  are averaged, or fitted by polynomials in amplitude and unwrapped phase over
+  a frequency coordinate mapped onto [-1, 1]; every channel of the band is
+  then damped towards the model (run_band).
 """
 from __future__ import annotations
 
@@ -407,6 +414,122 @@ def run(E: np.ndarray, pb: Problem, g0: np.ndarray, channels=None):
     return dict(image=np.stack([r["image"] for r in res]),
                 gains=np.stack([r["gains"] for r in res], axis=1),
                 held=np.stack([r["held"] for r in res], axis=1))
+
+
+# --------------------------------------------------------------------------
+# Gain solutions shared over a band of channels: the per-channel solutions
+# averaged across channels (Sec. 5, LWA demonstration) or fitted by low-order
+# polynomials in amplitude and phase over frequency (Sec. 6, fitting gain
+# models).  The paper gives no formulas; this is the reading used.
+# --------------------------------------------------------------------------
+
+def raw_solution(Kbar, Qbar, A, D, g, na, flags=None, d_tiny=1e-12):
+    """The undamped per-channel solution s_a = Na C_a / D_a (eq. Cna and
+    eq. cal_solution) and whether it is usable: not flagged, |D_a| above
+    d_tiny * max|D|, finite.  Returns (s, ok)."""
+    C = Kbar - np.conj(A) * Qbar / (na * np.conj(g))
+    with np.errstate(all="ignore"):
+        s = C * na / D
+    dmax = np.max(np.abs(D)) if D.size else 0.0
+    ok = (np.abs(D) > d_tiny * dmax) & np.isfinite(s)
+    if flags is not None:
+        ok &= np.asarray(flags) == 0
+    return s, ok
+
+
+def band_coordinate(freq_hz, b0: int, b1: int) -> np.ndarray:
+    """Frequency coordinate of the channels b0..b1-1 of a band, mapped
+    linearly onto [-1, 1] (first channel -1 for increasing frequencies; all
+    zero for a band of one channel)."""
+    nu = np.asarray(freq_hz[b0:b1], np.float64)
+    mid, half = 0.5 * (nu[0] + nu[-1]), 0.5 * (nu[-1] - nu[0])
+    return (nu - mid) / half if half != 0 else np.zeros_like(nu)
+
+
+def band_fit(sol, ok, x, mode: str, deg_amp: int = 0, deg_phase: int = 0):
+    """Model of the per-channel solutions of each antenna across a band.
+
+    sol, ok [Fb, Na]: solutions and usability (raw_solution) of the band's
+    channels in frequency order; x [Fb]: band_coordinate.
+      mode "mean": the mean of the usable solutions (Sec. 5);
+      mode "poly": |s| fitted by a polynomial of degree deg_amp in x, and the
+        phase, unwrapped along the usable channels in order, by one of degree
+        deg_phase (Sec. 6); the model is amp(x) exp(i phase(x)).
+    Least squares with equal weights.  An antenna needs at least one usable
+    channel (mean) or max(deg_amp, deg_phase) + 1 of them (poly).
+    Returns (model [Fb, Na] at every channel of the band, fit_ok [Na])."""
+    Fb, Na = sol.shape
+    model = np.zeros((Fb, Na), np.complex128)
+    fit_ok = np.zeros(Na, bool)
+    P = np.polynomial.polynomial
+    for a in range(Na):
+        v = ok[:, a]
+        if mode == "mean":
+            if v.sum() >= 1:
+                model[:, a] = sol[v, a].mean()
+                fit_ok[a] = True
+        elif mode == "poly":
+            if v.sum() < max(deg_amp, deg_phase) + 1:
+                continue
+            xs, s = x[v], sol[v, a]
+            ca = np.linalg.lstsq(np.vander(xs, deg_amp + 1, increasing=True), np.abs(s), rcond=None)[0]
+            cp = np.linalg.lstsq(np.vander(xs, deg_phase + 1, increasing=True), np.unwrap(np.angle(s)),
+                                 rcond=None)[0]
+            model[:, a] = P.polyval(x, ca) * np.exp(1j * P.polyval(x, cp))
+            fit_ok[a] = True
+        else:
+            raise ValueError(mode)
+    return model, fit_ok
+
+
+def run_band(E: np.ndarray, pb: Problem, g0: np.ndarray, band, mode: str = "mean",
+             deg_amp: int = 0, deg_phase: int = 0):
+    """The calibrated loop of all channels of one array, interval by interval,
+    with the gains of the channels band = (b0, b1) taken from the band model.
+
+    E [T, F, Na] uncalibrated.  Every channel is imaged, tapped and correlated
+    as in run_channel; at the end of an interval each channel's undamped
+    solution s_fa is formed (raw_solution).  Channels outside the band update
+    from their own s_fa; the band's channels from the band model m_fa
+    (band_fit), both damped as in eq. (damping):
+        g_fa <- (1 - gamma) target_fa + gamma g_fa.
+    A gain is held when its target is not usable (flagged antenna, no usable
+    solution, too few usable channels for the fit) or the update is not
+    finite.  Returns dict(image [F, ny, nx], gains [n_int + 1, F, Na],
+    held [n_int, F, Na])."""
+    F = len(pb.freq_hz)
+    b0, b1 = band
+    T = E.shape[0]
+    st = [channel_setup(pb, c) for c in range(F)]
+    x = band_coordinate(pb.freq_hz, b0, b1)
+    g = np.array(g0, np.complex128).copy()
+    Na = g.shape[1]
+    I = np.zeros((F, pb.ny, pb.nx), np.float64)
+    hist, held_hist = [g.copy()], []
+    for (t0, t1) in intervals(T, pb.t_cal):
+        nt = t1 - t0
+        sol = np.zeros((F, Na), np.complex128)
+        ok = np.zeros((F, Na), bool)
+        for c in range(F):
+            s = st[c]
+            Ec = calibrate(E[t0:t1, c], g[c], s["flags"])
+            X = dft2(grid(Ec, s["cells"], pb.nx, pb.ny), s["na"])
+            I[c] += (np.abs(X) ** 2).sum(axis=0)
+            P = X[:, s["k0"][1], s["k0"][0]]
+            K, Q = correlate(np.where(s["flags"] == 0, E[t0:t1, c], 0.0), P)
+            sol[c], ok[c] = raw_solution(K / nt, Q / nt, s["A"], s["D"], g[c], s["na"], s["flags"])
+        target, use = sol.copy(), ok.copy()
+        if b1 > b0:
+            model, fit_ok = band_fit(sol[b0:b1], ok[b0:b1], x, mode, deg_amp, deg_phase)
+            target[b0:b1] = model
+            use[b0:b1] = fit_ok[None, :] & (st[0]["flags"] == 0)[None, :]
+        with np.errstate(all="ignore"):
+            g_new = (1.0 - pb.gamma) * target + pb.gamma * g
+        held = ~use | ~np.isfinite(g_new)
+        g = np.where(held, g, g_new)
+        hist.append(g.copy())
+        held_hist.append(held)
+    return dict(image=I / T, gains=np.array(hist), held=np.array(held_hist))
 
 
 # --------------------------------------------------------------------------

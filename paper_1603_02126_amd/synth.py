@@ -164,6 +164,29 @@ def draw_gains(rng, n_chan, n_ant, amp_lo=0.8, amp_hi=1.2):
     return amp * np.exp(1j * ph)
 
 
+def bandpass_gains(rng, freq_hz, n_ant, amp_deg=0, phase_deg=0, turns=0.0, amp_lo=0.8, amp_hi=1.2):
+    """Gains that vary smoothly over frequency: per antenna an amplitude
+    a0 (1 + sum_k alpha_k x^k) and a phase phi0 + sum_k beta_k x^k, k >= 1,
+    with x the frequency mapped linearly onto [-1, 1] over all channels.
+    alpha_k ~ U[-0.1, 0.1]; beta_1 ~ U[-turns pi, turns pi] (a delay-like
+    slope: the phase winds up to `turns` times across the channels); higher
+    beta_k ~ U[-0.5, 0.5].  Degree 0 gives gains constant over the channels
+    (the narrow-band assumption of Sec. 5).  [F, Na] complex128."""
+    nu = np.asarray(freq_hz, np.float64)
+    span = nu.max() - nu.min()
+    x = (2.0 * (nu - nu.min()) / span - 1.0) if span > 0 else np.zeros_like(nu)
+    a0 = rng.uniform(amp_lo, amp_hi, size=n_ant)
+    ph0 = rng.uniform(0.0, 2 * np.pi, size=n_ant)
+    amp = np.ones((nu.size, n_ant))
+    ph = np.zeros((nu.size, n_ant))
+    for k in range(1, amp_deg + 1):
+        amp += rng.uniform(-0.1, 0.1, size=n_ant)[None, :] * x[:, None] ** k
+    for k in range(1, phase_deg + 1):
+        lim = turns * np.pi if k == 1 else 0.5
+        ph += rng.uniform(-lim, lim, size=n_ant)[None, :] * x[:, None] ** k
+    return a0[None, :] * amp * np.exp(1j * (ph0[None, :] + ph))
+
+
 def powerlaw_flux(rng, n, s_min, s_max):
     """dN/dS proportional to S^-2 on [s_min, s_max] (inverse CDF)."""
     u = rng.uniform(0.0, 1.0, size=n)

@@ -510,3 +510,131 @@ def test_multi_pixel_recovers_gains_from_unit_start():
     err = np.abs(_phase_ref(r["gains"][-1], wl.g_true[0]) - 1).max()
     assert err < 1e-10, err
     assert np.abs(_phase_ref(r["gains"][2], wl.g_true[0]) - 1).max() > 0.1
+
+
+# ---------------------------------------------------------------------------
+# gains shared over a band of channels (Sec. 5 averaging, Sec. 6 gain models)
+# ---------------------------------------------------------------------------
+
+def _band_case(n_chan, n_intervals, t_cal=16, amp_deg=0, phase_deg=0, turns=0.0, seed=3):
+    """Noiseless full-model sky (orthogonal source tones over each interval,
+    so the realised visibilities equal the model) over several channels, with
+    true gains that follow a given bandpass."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=n_chan, n_ant=24, t_cal=t_cal)
+    m = np.arange(1, wl.src_lmS.shape[0] + 1)
+    g = synth.bandpass_gains(np.random.default_rng(seed), wl.array.freq_hz, wl.array.n_ant, amp_deg, phase_deg, turns)
+    wl = wl.replace(amp_model="orthogonal", ortho_m=m, noise=False, model_lmS=wl.src_lmS, g_true=g,
+                    n_samples=t_cal * n_intervals)
+    E = np.stack([synth.efield_channel(wl, c) for c in range(n_chan)], axis=1)
+    return wl, E, O.Problem.from_workload(wl)
+
+
+@pytest.mark.parametrize("mode,deg", [("mean", 0), ("poly", 0)])
+def test_band_of_one_channel_is_the_per_channel_loop(mode, deg):
+    """A band of one channel: its model is its own solution (the mean of one
+    value; amplitude and phase of degree 0 reproduce it), so every channel
+    follows eq. (damping) alone."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=3, n_ant=20, n_samples=120, t_cal=30)
+    E = np.stack([synth.efield_channel(wl, c) for c in range(3)], axis=1)
+    pb = O.Problem.from_workload(wl)
+    per = O.run(E, pb, wl.g0)
+    band = O.run_band(E, pb, wl.g0, (1, 2), mode, deg, deg)
+    np.testing.assert_allclose(band["gains"], per["gains"], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(band["image"], per["image"], rtol=1e-12)
+
+
+def test_band_fit_reproduces_a_polynomial_bandpass():
+    """Amplitude of degree 2 and a phase of degree 3 that winds twice over the
+    band, a third of the channels unusable: the fit returns the bandpass at
+    every channel (the phase must be unwrapped, the unusable channels skipped
+    and evaluated)."""
+    rng = np.random.default_rng(4)
+    Fb, Na = 40, 6
+    x = np.linspace(-1, 1, Fb)
+    amp = 1.0 + rng.uniform(-0.2, 0.2, (3, Na))
+    amp = amp[0] + amp[1] * x[:, None] * 0.3 + amp[2] * x[:, None] ** 2 * 0.2
+    ph = rng.uniform(0, 6, Na) + 2.2 * np.pi * x[:, None] * np.array([1, -1, 1, -1, 1, -1]) \
+        + 0.4 * x[:, None] ** 3
+    truth = amp * np.exp(1j * ph)
+    ok = rng.uniform(size=(Fb, Na)) > 0.33
+    sol = np.where(ok, truth, np.nan + 0j)
+    model, fit_ok = O.band_fit(sol, ok, x, "poly", 2, 3)
+    assert fit_ok.all()
+    assert np.abs(model - truth).max() < 1e-10
+    # without unwrapping the same data do not fit
+    bad = np.zeros_like(truth)
+    for a in range(Na):
+        v = ok[:, a]
+        cp = np.polynomial.polynomial.polyfit(x[v], np.angle(truth[v, a]), 3)
+        bad[:, a] = np.exp(1j * np.polynomial.polynomial.polyval(x, cp))
+    assert np.abs(bad - truth / np.abs(truth)).max() > 0.1
+
+
+def test_band_fit_residuals_are_orthogonal():
+    """Least squares: the amplitude and unwrapped-phase residuals of noisy
+    solutions are orthogonal to every basis polynomial over the usable
+    channels; the mean leaves residuals that sum to zero."""
+    rng = np.random.default_rng(5)
+    Fb, Na = 30, 4
+    x = np.linspace(-1, 1, Fb)
+    sol = (1 + 0.1 * crandn(Fb, Na, rng=rng)) * np.exp(1j * (0.8 * x[:, None] + 0.05 * crandn(Fb, Na, rng=rng).real))
+    ok = rng.uniform(size=(Fb, Na)) > 0.2
+    model, _ = O.band_fit(sol, ok, x, "poly", 1, 2)
+    for a in range(Na):
+        v = ok[:, a]
+        ra = np.abs(sol[v, a]) - np.abs(model[v, a])
+        rp = np.angle(sol[v, a] / model[v, a])
+        for k in range(2):
+            assert abs(np.sum(ra * x[v] ** k)) < 1e-12
+        for k in range(3):
+            assert abs(np.sum(rp * x[v] ** k)) < 1e-12
+    mean, _ = O.band_fit(sol, ok, x, "mean")
+    for a in range(Na):
+        assert abs(np.sum(sol[ok[:, a], a] - mean[0, a])) < 1e-12
+
+
+def test_band_mean_recovers_gains_constant_over_frequency():
+    """Gains constant over the channels (Sec. 5's narrow band), noiseless
+    full-model sky, unit initial gains, all channels averaged: every channel
+    converges to the truth up to one global phase within 1e-10."""
+    wl, E, pb = _band_case(4, 150)
+    r = O.run_band(E, pb, wl.g0, (0, 4), "mean")
+    g = r["gains"][-1]
+    np.testing.assert_allclose(g, np.broadcast_to(g[0], g.shape), rtol=1e-14, atol=1e-14)
+    err = np.abs(_phase_ref(g, wl.g_true) - 1).max()
+    assert err < 1e-10, err
+    assert np.abs(_phase_ref(r["gains"][2], wl.g_true) - 1).max() > 0.1
+
+
+def test_band_poly_bandpass_is_a_fixed_point_and_attracts():
+    """A bandpass of amplitude degree 2 and phase degree 3 that winds over the
+    band: the exact gains are a fixed point of the fitted update, and from
+    gains 20% off the loop returns to them up to a common phase per channel."""
+    wl, E, pb = _band_case(6, 120, amp_deg=2, phase_deg=3, turns=1.5)
+    r = O.run_band(E[:pb.t_cal], pb.__class__(**{**pb.__dict__}), wl.g_true, (0, 6), "poly", 2, 3)
+    assert np.abs(r["gains"][-1] / wl.g_true - 1).max() < 1e-12
+    pert = 0.2 * crandn(*wl.g_true.shape, rng=np.random.default_rng(9))
+    r = O.run_band(E, pb, wl.g_true * (1 + pert), (0, 6), "poly", 2, 3)
+    err = np.abs(_phase_ref(r["gains"][-1], wl.g_true) - 1).max()
+    assert err < 1e-9, err
+
+
+def test_raw_solution_damped_is_the_paper_update():
+    """Damping the usable raw solutions reproduces gain_update (eq. damping),
+    including what it holds: a flagged antenna, a denominator below 1e-12 of
+    the largest, a zero denominator."""
+    rng = np.random.default_rng(31)
+    Na, na, gamma = 10, 9.0, 0.35
+    K, A, D = crandn(Na, rng=rng), crandn(Na, rng=rng), crandn(Na, rng=rng) * 4
+    D[3] = 1e-13 * np.abs(D).max()
+    D[5] = 0.0
+    Q = rng.uniform(1, 2, Na)
+    g = crandn(Na, rng=rng) + 1.5
+    flags = np.zeros(Na, np.uint8)
+    flags[7] = 1
+    s, ok = O.raw_solution(K, Q, A, D, g, na, flags)
+    want, held = O.gain_update(K, Q, A, D, g, na, gamma, flags)
+    assert list(np.flatnonzero(~ok)) == [3, 5, 7]
+    np.testing.assert_array_equal(held, ~ok)
+    damped = (1 - gamma) * np.where(ok, s, 0) + gamma * g
+    np.testing.assert_allclose(np.where(ok, damped, g), want, rtol=1e-15)

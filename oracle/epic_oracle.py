@@ -454,7 +454,8 @@ def band_fit(sol, ok, x, mode: str, deg_amp: int = 0, deg_phase: int = 0):
       mode "mean": the mean of the usable solutions (Sec. 5);
       mode "poly": |s| fitted by a polynomial of degree deg_amp in x, and the
         phase, unwrapped along the usable channels in order, by one of degree
-        deg_phase (Sec. 6); the model is amp(x) exp(i phase(x)).
+        deg_phase (Sec. 6); the model is amp(x) exp(i phase(x)).  A solution
+        of exactly zero has no phase and is not usable here.
     Least squares with equal weights.  An antenna needs at least one usable
     channel (mean) or max(deg_amp, deg_phase) + 1 of them (poly).
     Returns (model [Fb, Na] at every channel of the band, fit_ok [Na])."""
@@ -469,6 +470,7 @@ def band_fit(sol, ok, x, mode: str, deg_amp: int = 0, deg_phase: int = 0):
                 model[:, a] = sol[v, a].mean()
                 fit_ok[a] = True
         elif mode == "poly":
+            v = v & (sol[:, a] != 0)
             if v.sum() < max(deg_amp, deg_phase) + 1:
                 continue
             xs, s = x[v], sol[v, a]

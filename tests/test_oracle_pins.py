@@ -638,3 +638,28 @@ def test_raw_solution_damped_is_the_paper_update():
     np.testing.assert_array_equal(held, ~ok)
     damped = (1 - gamma) * np.where(ok, s, 0) + gamma * g
     np.testing.assert_allclose(np.where(ok, damped, g), want, rtol=1e-15)
+
+
+def test_band_fit_skips_zero_solutions():
+    """A solution of exactly zero (an antenna with all-zero samples over an
+    interval) has no phase: the polynomial model leaves it out whatever the
+    signs of its zeros, exactly as if the channel were unusable; the mean
+    keeps it."""
+    rng = np.random.default_rng(6)
+    Fb, Na = 8, 3
+    x = np.linspace(-1, 1, Fb)
+    sol = crandn(Fb, Na, rng=rng) + 2.0
+    ok = np.ones((Fb, Na), bool)
+    skipped = ok.copy()
+    skipped[3, 1] = False
+    want, _ = O.band_fit(sol, skipped, x, "poly", 1, 2)
+    for z in (complex(0.0, 0.0), complex(-0.0, 0.0), complex(0.0, -0.0), complex(-0.0, -0.0)):
+        s = sol.copy()
+        s[3, 1] = z
+        got, fit_ok = O.band_fit(s, ok, x, "poly", 1, 2)
+        assert fit_ok.all()
+        np.testing.assert_array_equal(got, want)
+    s = sol.copy()
+    s[3, 1] = 0.0
+    mean, _ = O.band_fit(s, ok, x, "mean")
+    assert abs(mean[0, 1] - s[:, 1].mean()) < 1e-15

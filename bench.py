@@ -105,6 +105,8 @@ def imaging_bytes_per_frame(na, bpe, n, n_samples, t_cal):
 def workload(name):
     if name == "lwa":
         return synth.config_lwa()
+    if name == "lwa_band":
+        return synth.config_lwa_band()
     if name == "hera":
         return synth.config_hera()
     if name == "tiny":
@@ -169,6 +171,35 @@ def cpu_baseline(wl, packed, budget_s, gpu_image=None, gpu_gains=None, extra_ima
                "gain_rel_err": max(gain_rel_err(gpu_gains[c], r["gains"][-1]) for c, r in results)}
         for name, im in (extra_images or {}).items():
             par[f"{name}_image_rel_err"] = max(rel_err(im[c], r["image"]) for c, r in results)
+    return out, par
+
+
+def cpu_baseline_band(wl, packed, budget_s, band, gpu_prefix):
+    """The FP64 oracle with gains shared over a band: the channels are
+    coupled, so the sample is every channel over the first intervals (one
+    interval timed first, then as many as the budget allows).  Parity: the
+    GPU run over the same prefix of samples."""
+    from oracle import epic_oracle as O
+    pb = O.Problem.from_workload(wl)
+    mode = {1: "mean", 2: "poly"}[band[2]]
+    n_int = -(-wl.n_samples // wl.t_cal)
+
+    def run(k):
+        E = O.unpack(packed[:k * wl.t_cal], wl.array.efmt)
+        t0 = time.perf_counter()
+        r = O.run_band(E, pb, wl.g0, band[:2], mode)
+        return r, time.perf_counter() - t0
+    k = 1
+    r, dt = run(1)
+    if dt < budget_s / 2 and n_int > 1:
+        k = int(min(n_int, max(2, budget_s // dt)))
+        r, dt = run(k)
+    frames = k * wl.t_cal * wl.array.n_chan
+    out = {"value": frames / dt, "unit": "frames/s", "cores": oracle_threads(), "kind": "oracle",
+           "sample": f"all {wl.array.n_chan} channels x the first {k} intervals ({frames} frames, {dt:.1f} s)"}
+    im, gh = gpu_prefix(k * wl.t_cal)
+    par = {"samples": k * wl.t_cal, "image_rel_err": max(rel_err(im[c], r["image"][c]) for c in range(im.shape[0])),
+           "gain_rel_err": max(gain_rel_err(gh[n], r["gains"][n]) for n in range(gh.shape[0]))}
     return out, par
 
 
@@ -237,9 +268,10 @@ def copy_reference(dev):
     print("# copy reference: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
 
 
-def new_plan(specs_wls, opts=None, pix=None):
+def new_plan(specs_wls, opts=None, pix=None, band=None):
     """A plan over the arrays of `specs_wls`; with `pix` the first array's
-    EPICal taps those pixels instead of its calibrator alone."""
+    EPICal taps those pixels instead of its calibrator alone; with
+    band = (b0, b1, mode) its channels b0..b1-1 share gains."""
     from paper_1603_02126_amd import lib
     plan = lib.Plan([w.array for w in specs_wls])
     for i, w in enumerate(specs_wls):
@@ -247,6 +279,8 @@ def new_plan(specs_wls, opts=None, pix=None):
             plan.set_model_pixels(i, w.model_lmS, pix, w.gamma, w.t_cal)
         else:
             plan.set_model(i, w.model_lmS, w.cal_lm, w.gamma, w.t_cal)
+    if band is not None:
+        plan.set_band(0, *band)
     for k, v in (opts or {}).items():
         plan.set_option(k, v)
     return plan
@@ -269,7 +303,9 @@ def bench_single(args, dev):
         # several tapped pixels: the brightest model sources (the calibrator first)
         order = np.argsort(-wl.model_lmS[:, 2], kind="stable")[:args.pixels]
         pix = wl.model_lmS[order, :2]
-    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None, pix)
+    # lwa_band: every channel shares the band's mean solution (Sec. 5)
+    band = (0, a.n_chan, lib.BAND_MEAN) if wl.name == "lwa_band" else None
+    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None, pix, band)
     e = torch.from_numpy(packed).to(dev)
     g0 = torch.from_numpy(wl.g0).to(dev)
     g = torch.empty_like(g0)
@@ -289,7 +325,7 @@ def bench_single(args, dev):
     if not args.no_forms:
         if a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512):
             # form 1: split-precision DFT-GEMM on the matrix cores, same workload
-            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2}, pix)
+            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2}, pix, band)
             img_d = torch.zeros_like(img)
             dt_d, tim_d = Timer([plan_d])(stepper(plan_d, img_d), args.steps, args.warmup)
             ms_img_d = tim_d[lib.TIMER_IMAGE][0] / max(1, tim_d[lib.TIMER_IMAGE][1])
@@ -305,7 +341,11 @@ def bench_single(args, dev):
         else:
             forms["dft_gemm_fp16_split"] = {"supported": False,
                                              "reason": "the DFT-GEMM form covers arrays of at most 512 antennas"}
-        # form 2: batched launches captured in a hipGraph, after autotuning
+    # form 2: batched launches captured in a hipGraph, after autotuning
+    if not args.no_forms and band is not None:
+        forms["batched_graph_autotuned"] = {"supported": False,
+                                            "reason": "gains shared over a band run in the per-array form"}
+    elif not args.no_forms:
         plan_g = new_plan([wl], None, pix)
         tuning = plan_g.autotune([e], wl.n_samples)
         plan_g.set_option(lib.OPT_BATCH, 1)
@@ -338,7 +378,18 @@ def bench_single(args, dev):
                "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)}
 
     cpu, parity = None, None
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and band is not None:
+        print("# timing the FP64 oracle on the host (all channels, first intervals)", file=sys.stderr, flush=True)
+
+        def gpu_prefix(n_s):
+            gh = torch.zeros((-(-n_s // wl.t_cal) + 1, a.n_chan, a.n_ant), dtype=torch.complex128, device=dev)
+            im = torch.zeros_like(img)
+            g.copy_(g0)
+            plan.run([e], n_s, [g], [im], gain_hist=[gh])
+            torch.cuda.synchronize()
+            return im.cpu().numpy(), gh.cpu().numpy()
+        cpu, parity = cpu_baseline_band(wl, packed, args.cpu_budget, band, gpu_prefix)
+    elif args.cpu_budget > 0:
         print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         extra = {k: v["_image"].cpu().numpy() for k, v in forms.items() if "_image" in v}
         cpu, parity = cpu_baseline(wl, packed, args.cpu_budget, img.cpu().numpy(), gains_plain, extra, pix)
@@ -350,7 +401,8 @@ def bench_single(args, dev):
     out = base_record(args, value, ms_step, "f32", {
         "workload": describe(wl), "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan,
         "grid": [a.ny, a.nx], "n_samples": wl.n_samples, "t_cal": wl.t_cal, "efmt": synth.FMT_NAMES[a.efmt],
-        "path": "plain FP32 FFT", "parallelism": "1 GPU", "tapped_pixels": args.pixels})
+        "path": "plain FP32 FFT", "parallelism": "1 GPU", "tapped_pixels": args.pixels,
+        "band": None if band is None else {"channels": [band[0], band[1]], "mode": "mean"}})
     out.update({
         "msamples_per_s": value * a.n_ant / 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -558,7 +610,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lwa", choices=["lwa", "hera", "tiny", "uneven", "diff"])
+    ap.add_argument("--workload", default="lwa", choices=["lwa", "lwa_band", "hera", "tiny", "uneven", "diff"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")

@@ -60,6 +60,8 @@ typedef enum {
 #define EPIC_ANT_FLAGGED 1u    /* flagged on input: not gridded/correlated/updated */
 #define EPIC_ANT_D_ZERO 2u     /* |D_a| <= 1e-12 max|D|: gain held */
 #define EPIC_ANT_NONFINITE 4u  /* update not finite: gain held */
+#define EPIC_ANT_BAND_HELD 8u  /* band model without enough usable channels: gain held */
+#define EPIC_ANT_BARRIER 16u   /* band solve: a grid barrier did not complete (gains NaN) */
 
 /* One antenna array and its aperture grid (Sec. 2.1, eq. gridding).
  * Positions and grid are in metres.  Grid cell (jx, jy) sits at
@@ -131,6 +133,12 @@ int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* mod
 int epic_host_calibrator_pixels(const epic_array_desc* desc, const epic_model_desc* model, const double* pix_lm,
                                 int32_t n_pix, int32_t* k0, double* A, double* D);
 
+/* The band coordinate of epical_set_band: host x[F], the frequencies of
+ * channels b0..b1-1 mapped linearly onto [-1, 1] in channel order
+ * (x = (f - mid) / half, mid and half from the first and last channel of the
+ * band; all 0 for a band of one channel), 0 outside the band. */
+int epic_host_band_coordinate(const epic_array_desc* desc, int32_t b0, int32_t b1, double* x);
+
 /* ---------------------------------------------------------------------- */
 /* Plans                                                                   */
 /* ---------------------------------------------------------------------- */
@@ -169,6 +177,42 @@ int epical_set_model(epic_plan_t plan, int32_t array, const epic_model_desc* mod
 #define EPIC_MAX_PIX 4
 int epical_set_model_pixels(epic_plan_t plan, int32_t array, const epic_model_desc* model, const double* pix_lm,
                             int32_t n_pix);
+
+/* Gains shared over a band of channels (Sec. 5: solutions averaged across
+ * the central channels of the LWA band; Sec. 6: fitting a gain model, a
+ * low-order polynomial in amplitude and phase over frequency).  The paper
+ * gives no formulas; the reading used is stated here.
+ *   mode EPIC_BAND_NONE   every channel updates from its own solution (default);
+ *   mode EPIC_BAND_MEAN   the channels b0..b1-1 share the mean of their solutions;
+ *   mode EPIC_BAND_POLY   the channels b0..b1-1 take amp(x) exp(i phase(x)), with
+ *                         |s| fitted by a polynomial of degree deg_amp and the
+ *                         phase, unwrapped along the usable channels in channel
+ *                         order, by one of degree deg_phase (0..EPIC_BAND_MAX_DEG),
+ *                         least squares with equal weights; a solution of
+ *                         exactly zero has no phase and is left out.
+ * Here s_fa = Na C_fa / D_fa is channel f's undamped solution (eq. Cna,
+ * eq. cal_solution) at the end of an interval, and x the band coordinate:
+ * the band's frequencies mapped linearly onto [-1, 1] in channel order
+ * (epic_host_band_coordinate).  Every channel of the band is then damped
+ * towards the model as in eq. (damping): g_fa <- (1 - gamma) m_fa + gamma g_fa;
+ * channels outside the band keep their own update.  A channel's solution is
+ * left out where the antenna is held (flagged, |D| below 1e-12 of the
+ * largest, not finite); an antenna with no usable channel (mean) or fewer
+ * than max(deg_amp, deg_phase) + 1 of them (poly) keeps its gains in the band
+ * (EPIC_ANT_BAND_HELD).  The polynomial model needs strictly monotonic frequencies
+ * over the band.  epic_run then solves all channels of the array in one
+ * cooperative launch (every workgroup resident, grid-wide barriers between
+ * the per-channel solutions, the band model and the update; a barrier that
+ * does not complete leaves NaN gains and EPIC_ANT_BARRIER).  Needs Na <= 1024,
+ * one tapped pixel and the per-array form (EPIC_OPT_BATCH 0 or 2, no
+ * EPIC_OPT_GRAPH), else EPIC_ERR_UNSUPPORTED; epical_update then returns
+ * EPIC_ERR_UNSUPPORTED.  b0, b1 are ignored for EPIC_BAND_NONE. */
+#define EPIC_BAND_NONE 0
+#define EPIC_BAND_MEAN 1
+#define EPIC_BAND_POLY 2
+#define EPIC_BAND_MAX_DEG 3
+int epical_set_band(epic_plan_t plan, int32_t array, int32_t b0, int32_t b1, int32_t mode, int32_t deg_amp,
+                    int32_t deg_phase);
 
 /* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)

@@ -367,6 +367,9 @@ struct ArrayPlan {
   double2* d_D = nullptr;      // [n_pix][F][Na]
   uint8_t* d_hold = nullptr;
   int n_pix = 1;
+  // gains shared over a band of channels (epical_set_band)
+  int band_mode = 0, band_b0 = 0, band_b1 = 0, band_deg_amp = 0, band_deg_phase = 0;
+  double* d_band_x = nullptr;  // [F] band coordinate
 };
 
 struct TimerRec {
@@ -426,6 +429,7 @@ void free_array(ArrayPlan& p) {
   hipFree(p.d_A);
   hipFree(p.d_D);
   hipFree(p.d_hold);
+  hipFree(p.d_band_x);
   p = ArrayPlan{};
 }
 
@@ -583,6 +587,44 @@ int epic_host_calibrator(const epic_array_desc* desc, const epic_model_desc* mod
   return EPIC_OK;
 }
 
+// Band coordinate: the band's frequencies mapped linearly onto [-1, 1] in
+// channel order (0 outside the band, and for a band of one channel).
+static void band_coordinate(const HostArray& h, int b0, int b1, std::vector<double>& x) {
+  x.assign(h.F, 0.0);
+  const double lo = h.freq[b0], hi = h.freq[b1 - 1];
+  const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+  if (half != 0)
+    for (int f = b0; f < b1; ++f) x[f] = (h.freq[f] - mid) / half;
+}
+
+static int check_band(const HostArray& h, int b0, int b1, int mode, int deg_amp, int deg_phase) {
+  if (mode == EPIC_BAND_NONE) return EPIC_OK;
+  if (mode != EPIC_BAND_MEAN && mode != EPIC_BAND_POLY) return fail(EPIC_ERR_ARG, "unknown band mode %d", mode);
+  if (b0 < 0 || b1 <= b0 || b1 > h.F)
+    return fail(EPIC_ERR_ARG, "band [%d, %d) must be a non-empty range of the %d channels", b0, b1, h.F);
+  if (mode == EPIC_BAND_POLY) {
+    if (deg_amp < 0 || deg_amp > EPIC_BAND_MAX_DEG || deg_phase < 0 || deg_phase > EPIC_BAND_MAX_DEG)
+      return fail(EPIC_ERR_ARG, "band polynomial degrees must be in [0, %d]", EPIC_BAND_MAX_DEG);
+    const bool up = h.freq[b1 - 1] >= h.freq[b0];
+    for (int f = b0 + 1; f < b1; ++f)
+      if (up ? !(h.freq[f] > h.freq[f - 1]) : !(h.freq[f] < h.freq[f - 1]))
+        return fail(EPIC_ERR_ARG, "the band's frequencies must be strictly monotonic for the polynomial model");
+  }
+  return EPIC_OK;
+}
+
+int epic_host_band_coordinate(const epic_array_desc* desc, int32_t b0, int32_t b1, double* x) {
+  HostArray h;
+  int rc = check_desc(desc, &h);
+  if (rc) return rc;
+  if (!x) return fail(EPIC_ERR_ARG, "x must not be NULL");
+  if ((rc = check_band(h, b0, b1, EPIC_BAND_MEAN, 0, 0))) return rc;
+  std::vector<double> v;
+  band_coordinate(h, b0, b1, v);
+  std::memcpy(x, v.data(), v.size() * sizeof(double));
+  return EPIC_OK;
+}
+
 int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_t* out) {
   if (!out) return fail(EPIC_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -725,6 +767,31 @@ static int set_model_tables(epic_plan_t plan, int32_t array, const epic_model_de
   return EPIC_OK;
 }
 
+int epical_set_band(epic_plan_t plan, int32_t array, int32_t b0, int32_t b1, int32_t mode, int32_t deg_amp,
+                    int32_t deg_phase) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if ((rc = check_band(ap.h, b0, b1, mode, deg_amp, deg_phase))) return rc;
+  if (mode != EPIC_BAND_NONE && !epic::band_supported(ap.h.na, ap.h.efmt))
+    return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band need Na <= 1024 (got %d)", ap.h.na);
+  hipFree(ap.d_band_x);
+  ap.d_band_x = nullptr;
+  ap.band_mode = EPIC_BAND_NONE;
+  if (mode != EPIC_BAND_NONE) {
+    std::vector<double> x;
+    band_coordinate(ap.h, b0, b1, x);
+    if ((rc = upload(&ap.d_band_x, x.data(), x.size()))) return rc;
+    ap.band_mode = mode;
+    ap.band_b0 = b0;
+    ap.band_b1 = b1;
+    ap.band_deg_amp = mode == EPIC_BAND_POLY ? deg_amp : 0;
+    ap.band_deg_phase = mode == EPIC_BAND_POLY ? deg_phase : 0;
+  }
+  plan->generation++;
+  return EPIC_OK;
+}
+
 int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
   if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
   switch (key) {
@@ -814,6 +881,9 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
   if (ap.n_pix != 1)
     return fail(EPIC_ERR_UNSUPPORTED, "the stage-wise update takes one tap per sample; this array has %d pixels "
                 "(use epic_run)", ap.n_pix);
+  if (ap.band_mode != EPIC_BAND_NONE)
+    return fail(EPIC_ERR_UNSUPPORTED, "the stage-wise update is per channel; this array shares gains over a band "
+                "(use epic_run)");
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (!kq || !gains) return fail(EPIC_ERR_ARG, "kq and gains must not be NULL");
   if (nt > 0 && (!efield || !tap)) return fail(EPIC_ERR_ARG, "efield and tap must not be NULL");
@@ -857,6 +927,7 @@ struct RunLayout {
   int64_t n_int;
   int splits;
   size_t u_off, p_off, gh_off;   // gh_off: gain history when the caller passes none
+  size_t band_off;               // band solve: raw solutions [F][Na], model [Na][8], barrier counter
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -947,7 +1018,26 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       ArrayPlan& ap = plan->arrays[i];
       {
         Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
-        hipError_t e = epic::launch_solve(sa[i], s);
+        hipError_t e;
+        if (ap.band_mode != EPIC_BAND_NONE) {
+          const HostArray& h = ap.h;
+          char* bp = scr + lay[i].band_off;
+          epic::BandArgs b{};
+          b.s = sa[i];
+          b.b0 = ap.band_b0;
+          b.b1 = ap.band_b1;
+          b.mode = ap.band_mode;
+          b.deg_amp = ap.band_deg_amp;
+          b.deg_phase = ap.band_deg_phase;
+          b.x = ap.d_band_x;
+          b.raw = reinterpret_cast<double2*>(bp);
+          b.coef = reinterpret_cast<double*>(bp + align256(size_t(h.F) * h.na * sizeof(double2)));
+          b.bar = reinterpret_cast<uint32_t*>(bp + align256(size_t(h.F) * h.na * sizeof(double2)) +
+                                              align256(size_t(h.na) * epic::kBandCoef * sizeof(double)));
+          e = epic::launch_solve_band(b, plan->n_cu, s);
+        } else {
+          e = epic::launch_solve(sa[i], s);
+        }
         if (e == hipSuccess) e = hist_to_u(i);
         if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
       }
@@ -1036,6 +1126,7 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   std::vector<RunLayout> lay(na_arr);
   size_t need = 0;
   bool all_batchable = na_arr <= epic::kMaxBatch;
+  bool any_band = false;
   for (int i = 0; i < na_arr; ++i) {
     int rc = check_plan(plan, i);
     if (rc) return rc;
@@ -1054,9 +1145,18 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     need += align256(size_t(lay[i].splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float));
     lay[i].gh_off = need;
     need += align256(size_t(lay[i].n_int + 1) * ap.h.F * ap.h.na * sizeof(double2));
+    lay[i].band_off = need;
+    if (ap.band_mode != EPIC_BAND_NONE) {
+      if (ap.n_pix != 1) return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band take one tapped pixel");
+      any_band = true;
+      need += align256(size_t(ap.h.F) * ap.h.na * sizeof(double2)) +
+              align256(size_t(ap.h.na) * epic::kBandCoef * sizeof(double)) + 256;
+    }
     all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
-  const bool batched = all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));
+  if (any_band && plan->batch == 1)
+    return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band run in the per-array form (EPIC_OPT_BATCH 0 or 2)");
+  const bool batched = !any_band && all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));
   if (plan->graph && !batched)
     return fail(EPIC_ERR_UNSUPPORTED, "graph replay needs the batched form (EPIC_OPT_BATCH and supported engines)");
   void* scr = nullptr;

@@ -74,6 +74,23 @@ struct SolveArgs {
 };
 constexpr int kMaxPix = 4;
 
+// Gains shared over a band of channels.  Band model per antenna: mean mode
+// (re, im); poly mode 4 amplitude and 4 phase coefficients (increasing
+// powers of x).  NaN in slot 0: no model.
+constexpr int kBandCoef = 8;
+constexpr int kBandMaxDeg = 3;
+enum : int { kBandNone = 0, kBandMean = 1, kBandPoly = 2 };
+
+struct BandArgs {
+  SolveArgs s;
+  int b0, b1;               // band channels [b0, b1)
+  int mode, deg_amp, deg_phase;
+  const double* x;          // [F] band coordinate in [-1, 1] (band channels)
+  double2* raw;             // [F][Na] undamped solutions of the current interval (NaN: none)
+  double* coef;             // [Na][kBandCoef] band model of the current interval
+  uint32_t* bar;            // grid barrier counter, zero at launch
+};
+
 // Stage-wise EPICal accumulate / finalize.
 struct UpdateArgs {
   const uint8_t* efield;
@@ -163,6 +180,9 @@ hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, do
                          float* image, hipStream_t s);
 bool solve_supported(int na, int fmt, int n_pix = 1);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+bool band_supported(int na, int fmt);
+// cooperative launch; *groups receives the number of workgroups
+hipError_t launch_solve_band(const BandArgs& b, int n_cu, hipStream_t s, int* groups = nullptr);
 // u_hist[n] = 1 / g_hist[n] (FP64, rounded to FP32; zero for flagged antennas), n < n_int
 hipError_t launch_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_int, int F, int Na, float2* u_hist,
                             hipStream_t s);

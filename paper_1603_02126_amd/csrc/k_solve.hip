@@ -1,5 +1,8 @@
 // HIP kernels (gfx950): EPICal calibration solve (tap, correlation, damped FP64 update).
+#include <algorithm>
+
 #include "solve.h"
+#include "solve_band.h"
 
 namespace epic {
 
@@ -95,6 +98,76 @@ hipError_t launch_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t 
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hist_to_u, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, g_hist, hold, n, per, u_hist);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gains shared over a band of channels: one cooperative launch, every
+// workgroup resident, channels f = blockIdx.x + k * gridDim.x.  Per interval:
+// each channel's undamped solution (band_interval), a grid barrier, the band
+// model of every antenna (one wave per antenna), a grid barrier, and each
+// channel's damped update (band_apply).
+// ---------------------------------------------------------------------------
+template <int PS, int FMT>
+__global__ __launch_bounds__(kSolveThreads) void k_solve_band(BandArgs b) {
+  __shared__ __align__(16) uint8_t smem[BandSmem::BYTES];
+  __shared__ int s_ok;
+  const SolveArgs& a = b.s;
+  const int G = gridDim.x, wave = threadIdx.x >> 6;
+  uint32_t target = 0;
+  for (int n = 0; n < a.n_int; ++n) {
+    for (int f = blockIdx.x; f < a.F; f += G) band_interval<PS, FMT>(b, f, n, smem);
+    target += uint32_t(G);
+    if (!grid_barrier(b.bar, target, &s_ok)) {
+      band_abort(b);
+      return;
+    }
+    for (int ant = wave * G + blockIdx.x; ant < a.Na; ant += (kSolveThreads / 64) * G) band_fit_antenna(b, ant);
+    target += uint32_t(G);
+    if (!grid_barrier(b.bar, target, &s_ok)) {
+      band_abort(b);
+      return;
+    }
+    for (int f = blockIdx.x; f < a.F; f += G) band_apply(b, f, n);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+bool band_supported(int na, int fmt) { return na >= 1 && na <= kSolveThreads && solve_supported(na, fmt, 1); }
+
+template <int PS>
+static const void* band_kernel(int fmt) {
+  if (fmt == kCI4) return reinterpret_cast<const void*>(&k_solve_band<PS, kCI4>);
+  if (fmt == kCI8) return reinterpret_cast<const void*>(&k_solve_band<PS, kCI8>);
+  return reinterpret_cast<const void*>(&k_solve_band<PS, kCF32>);
+}
+
+hipError_t launch_solve_band(const BandArgs& b, int n_cu, hipStream_t s, int* groups) {
+  const SolveArgs& a = b.s;
+  if (!band_supported(a.Na, a.fmt) || a.n_pix != 1 || b.b0 < 0 || b.b1 <= b.b0 || b.b1 > a.F)
+    return hipErrorInvalidValue;
+  if (b.mode == kBandPoly && (b.deg_amp < 0 || b.deg_amp > kBandMaxDeg || b.deg_phase < 0 ||
+                              b.deg_phase > kBandMaxDeg))
+    return hipErrorInvalidValue;
+  if (b.mode != kBandMean && b.mode != kBandPoly) return hipErrorInvalidValue;
+  const int RB = a.Na * efmt_bytes(a.fmt);
+  const void* fn = RB % 16 == 0 ? band_kernel<16>(a.fmt) : RB % 4 == 0 ? band_kernel<4>(a.fmt) : band_kernel<1>(a.fmt);
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int G = std::min(a.F, per_cu * n_cu);
+  if (groups) *groups = G;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, b.bar, 1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BandArgs arg = b;
+  void* args[] = {&arg};
+  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(kSolveThreads), args, 0, s);
 }
 
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {

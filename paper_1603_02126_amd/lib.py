@@ -25,7 +25,8 @@ _NAMES = {EPIC_ERR_ARG: "EPIC_ERR_ARG", EPIC_ERR_ALLOC: "EPIC_ERR_ALLOC", EPIC_E
 CF32, CI8, CI4 = 0, 1, 2
 OPT_SPLITS, OPT_TRANSFORM, OPT_TIMING, OPT_BATCH, OPT_GRAPH = 1, 2, 3, 4, 5
 TIMER_SOLVE, TIMER_IMAGE, TIMER_REDUCE, TIMER_ADJOINT, TIMER_GRAPH, TIMER_COUNT = 0, 1, 2, 3, 4, 5
-ANT_FLAGGED, ANT_D_ZERO, ANT_NONFINITE = 1, 2, 4
+ANT_FLAGGED, ANT_D_ZERO, ANT_NONFINITE, ANT_BAND_HELD, ANT_BARRIER = 1, 2, 4, 8, 16
+BAND_NONE, BAND_MEAN, BAND_POLY, BAND_MAX_DEG = 0, 1, 2, 3
 
 
 class EpicError(RuntimeError):
@@ -64,6 +65,10 @@ _SIGS = {
     "epic_host_calibrator_pixels": (ctypes.c_int, [ctypes.POINTER(ArrayDesc), ctypes.POINTER(ModelDesc),
                                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_void_p]),
+    "epical_set_band": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "epic_host_band_coordinate": (ctypes.c_int, [ctypes.POINTER(ArrayDesc), ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_void_p]),
     "epic_plan_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
     "epic_plan_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "epic_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -186,6 +191,14 @@ def host_calibrator_pixels(spec, model_lmS, pix_lm, gamma=0.5, t_cal=1):
     return k0, A, D
 
 
+def host_band_coordinate(spec, b0, b1):
+    """x [F]: the band coordinate of epical_set_band."""
+    d = _DescHolder(spec)
+    x = np.zeros(d.freq.shape[0], np.float64)
+    _check(load().epic_host_band_coordinate(ctypes.byref(d.desc), int(b0), int(b1), x.ctypes.data))
+    return x
+
+
 # --------------------------------------------------------------------------
 # device plan
 # --------------------------------------------------------------------------
@@ -276,6 +289,11 @@ class Plan:
                                               int(pix.shape[0])))
         m.pix = pix
         self._models[array] = m
+
+    def set_band(self, array: int, b0: int, b1: int, mode: int, deg_amp: int = 0, deg_phase: int = 0):
+        """epical_set_band: gains shared over channels b0..b1-1 (BAND_MEAN / BAND_POLY; BAND_NONE clears)."""
+        _check(load().epical_set_band(self._h, int(array), int(b0), int(b1), int(mode), int(deg_amp),
+                                      int(deg_phase)))
 
     def set_option(self, key: int, value: int):
         _check(load().epic_plan_set_option(self._h, int(key), int(value)))

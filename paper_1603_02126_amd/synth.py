@@ -392,6 +392,22 @@ def config_lwa(seed: int = 2, n_chan: int = 128, n_samples: int = 10000, **over)
     return wl.replace(**over) if over else wl
 
 
+def config_lwa_band(seed: int = 2, n_chan: int = 128, n_samples: int = 10000, **over) -> Workload:
+    """The lwa shape with the choices of the LWA demonstration of Sec. 5:
+    gains constant over the band (one complex gain per antenna), initial
+    gains 0.25, gamma = 0.7.  Calibrated with every channel sharing the band's
+    mean solution."""
+    base = config_lwa(seed, n_chan, n_samples)
+    s_g = _rng(_streams(seed + 1000)[1])
+    g = bandpass_gains(s_g, base.array.freq_hz, base.array.n_ant)
+    qs = _quant_scale(base.src_lmS[:, 2], base.sigma_r, g, 2.0)
+    model = base.src_lmS.copy()
+    model[:, 2] /= qs * qs
+    wl = base.replace(name="lwa_band", g_true=g, quant_scale=qs, model_lmS=model,
+                      g0=np.full((n_chan, base.array.n_ant), 0.25, np.complex128), gamma=0.7)
+    return wl.replace(**over) if over else wl
+
+
 def config_hera(seed: int = 3, n_chan: int = 512, n_samples: int = 2000, **over) -> Workload:
     """HERA shape: 350 antennas on a 14 m hexagonal lattice, 8+8-bit E-fields,
     channels across 100-200 MHz, 128x128 grid of 2.5 m cells (origin offset a
@@ -468,6 +484,7 @@ def config_small(seed: int = 11, n_ant: int = 48, n: int = 32, n_chan: int = 3, 
 CONFIGS = {
     "tiny": config_tiny,
     "lwa": config_lwa,
+    "lwa_band": config_lwa_band,
     "hera": config_hera,
     "diff": config_diff,
     "small": config_small,

@@ -3,6 +3,7 @@ header declares, and its host-side plan logic (grid cells, calibrator pixel,
 pixel response, model denominator, argument checks) agrees with the oracle.
 No device work is done here."""
 import ctypes
+import dataclasses
 
 import numpy as np
 import pytest
@@ -142,3 +143,28 @@ def test_pixel_count_errors(n_pix):
         m = lib._ModelHolder(wl.model_lmS, wl.cal_lm, 0.5, 10)
         lib._check(lib.load().epic_host_calibrator_pixels(ctypes.byref(d.desc), ctypes.byref(m.desc),
                                                           pix.ctypes.data, n_pix, None, None, None))
+
+
+@pytest.mark.parametrize("b0,b1", [(0, 5), (1, 4), (2, 3)])
+def test_band_coordinate_matches_oracle(b0, b1):
+    """The library's band coordinate (epical_set_band) against the oracle's."""
+    wl = synth.config_small(n_chan=5)
+    got = lib.host_band_coordinate(wl.array, b0, b1)
+    want = np.zeros(5)
+    want[b0:b1] = O.band_coordinate(wl.array.freq_hz, b0, b1)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+
+
+def test_band_coordinate_reversed_frequencies():
+    wl = synth.config_small(n_chan=4)
+    arr = dataclasses.replace(wl.array, freq_hz=wl.array.freq_hz[::-1].copy())
+    got = lib.host_band_coordinate(arr, 0, 4)
+    np.testing.assert_allclose(got, O.band_coordinate(arr.freq_hz, 0, 4), atol=1e-15)
+    assert got[0] == -1.0 and got[-1] == 1.0
+
+
+@pytest.mark.parametrize("b0,b1", [(-1, 2), (2, 2), (3, 1), (0, 6)])
+def test_band_range_errors(b0, b1):
+    wl = synth.config_small(n_chan=5)
+    with pytest.raises(lib.EpicError):
+        lib.host_band_coordinate(wl.array, b0, b1)

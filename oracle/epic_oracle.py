@@ -47,6 +47,10 @@ listed with its reason in the design notes of the repository):
   excludes b = a), not Na S_src.
 * Several tapped pixels (Sec. 6): the gain is the least-squares solution over
   the pixels of Na C_ap = g_a D_ap, damped (gain_update_multi).
+* The visibility-based comparison calibrator of Sec. 4 minimises eq.
+  (vis_cal) by alternating least squares (StEFCal); sigma_g of eq.
+  (gain_error) is taken after removing each channel's unobservable global
+  phase.
 * Gains shared over a band of channels (Sec. 5 averaging, Sec. 6 gain-model
   fitting): the undamped per-channel solutions Na C/D of the band's channels
   are averaged, or fitted by polynomials in amplitude and unwrapped phase over
@@ -532,6 +536,88 @@ def run_band(E: np.ndarray, pb: Problem, g0: np.ndarray, band, mode: str = "mean
         hist.append(g.copy())
         held_hist.append(held)
     return dict(image=I / T, gains=np.array(hist), held=np.array(held_hist))
+
+
+# --------------------------------------------------------------------------
+# The visibility-based comparison calibrator and the gain error of Sec. 4
+# --------------------------------------------------------------------------
+
+def visibilities(E: np.ndarray) -> np.ndarray:
+    """V_ab = <E_a E_b*> over the samples of E [T, Na]: every antenna pair
+    correlated over the window (Sec. 4 correlates for the effective
+    integration time of the EPICal loop)."""
+    E = np.asarray(E, np.complex128)
+    return (E.T @ np.conj(E)) / E.shape[0]
+
+
+def vis_chi2(V, VM, g) -> float:
+    """chi^2 = sum_a sum_{b != a} |V_ab - g_a g_b* V^M_ab|^2 (eq. vis_cal)."""
+    R = V - np.outer(g, np.conj(g)) * VM
+    np.fill_diagonal(R, 0.0)
+    return float(np.sum(np.abs(R) ** 2))
+
+
+def vis_chi2_gains(V, VM, g0, n_iter: int = 2000, tol: float = 1e-14):
+    """Gains that minimise eq. (vis_cal), by alternating least squares in the
+    form of StEFCal (Salvini & Wijnholds 2014).  With the other gains fixed,
+    chi^2 is quadratic in g_a (V and V^M are Hermitian, so the b-a terms
+    repeat the a-b ones): with z_ab = g_b* V^M_ab it is minimised by
+        g_a = sum_{b != a} conj(z_ab) V_ab / sum_{b != a} |z_ab|^2.
+    Every antenna is updated from the previous iterate and every second
+    update is averaged with it (which makes the iteration converge).  Stops
+    when the largest relative change is below tol.  The global phase is not
+    determined by chi^2; it is whatever the iteration from g0 reaches."""
+    g = np.array(g0, np.complex128).copy()
+    off = ~np.eye(V.shape[0], dtype=bool)
+    for it in range(n_iter):
+        Z = VM * np.conj(g)[None, :] * off
+        g_new = np.sum(np.conj(Z) * V, axis=1) / np.sum(np.abs(Z) ** 2, axis=1)
+        if it % 2 == 1:
+            g_new = 0.5 * (g_new + g)
+        done = np.max(np.abs(g_new - g)) <= tol * np.max(np.abs(g_new))
+        g = g_new
+        if done:
+            break
+    return g
+
+
+def gain_error(g_est: np.ndarray, g_true: np.ndarray) -> float:
+    """sigma_g of eq. (gain_error): the rms over channels and antennas of
+    |g_est - g_true| / |g_true|.  g [F, Na].  The global phase of a channel's
+    gains is unobservable (every calibrator here fixes it only through its
+    starting point), so each channel's estimate is first rotated by the
+    common phase that minimises its error."""
+    g_est = np.atleast_2d(g_est)
+    g_true = np.atleast_2d(g_true)
+    w = 1.0 / np.abs(g_true) ** 2
+    c = np.sum(w * np.conj(g_est) * g_true, axis=1)
+    rot = np.where(np.abs(c) > 0, c / np.where(np.abs(c) > 0, np.abs(c), 1.0), 1.0)
+    err = np.abs(g_est * rot[:, None] - g_true) ** 2 * w
+    return float(np.sqrt(np.mean(err)))
+
+
+def effective_time(t_cal: float, gamma: float) -> float:
+    """t_eff = t_cal (1 + gamma) / (1 - gamma) (eq. teff)."""
+    return t_cal * (1.0 + gamma) / (1.0 - gamma)
+
+
+def epical_gains(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, setup=None):
+    """The EPICal recursion of run_channel without forming images: the tap of
+    each sample is the beamformed sum P = (1/Na) sum_a A_a(k0) E_a / g_a (the
+    transform evaluated at k0; the identity is pinned against the imaged
+    tap), then eq. (Kna_def), eq. (Cna) and eq. (damping) as in run_channel.
+    Returns the gains [n_int + 1, Na]."""
+    s = channel_setup(pb, ch) if setup is None else setup
+    A, D, na, flags = s["A"], s["D"], s["na"], s["flags"]
+    g = np.array(g0, np.complex128).copy()
+    hist = [g.copy()]
+    for (t0, t1) in intervals(E.shape[0], pb.t_cal):
+        Ec = calibrate(E[t0:t1], g, flags)
+        P = (Ec @ A) / na
+        K, Q = correlate(np.where(flags == 0, E[t0:t1], 0.0), P)
+        g, _ = gain_update(K / (t1 - t0), Q / (t1 - t0), A, D, g, na, pb.gamma, flags)
+        hist.append(g.copy())
+    return np.array(hist)
 
 
 # --------------------------------------------------------------------------

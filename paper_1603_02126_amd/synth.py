@@ -408,6 +408,34 @@ def config_lwa_band(seed: int = 2, n_chan: int = 128, n_samples: int = 10000, **
     return wl.replace(**over) if over else wl
 
 
+def config_noise(seed: int = 9, sigma_r: float = 10.0, t_cal: int = 100, n_iter: int = 10, n_chan: int = 64,
+                 model: str = "full", **over) -> Workload:
+    """The noise-trend study of Sec. 4: 51 antennas uniform in a 48 m square
+    (a stand-in for the inner MWA layout of Sec. 3), n_chan channels over
+    140-160 MHz with fluxes constant over frequency, complex float samples in
+    Jy.  Sky: a 5 Jy calibrator at the phase centre and 49 sources of
+    0.2-0.5 Jy uniform within 0.5 of it (about 22 Jy in total; the
+    calibrator carries about 22%).  True gains 1 and g(0) = 1, gamma = 0.35,
+    receiver noise sigma_r, n_iter updates of t_cal samples.  model "full"
+    puts every source in the calibration model, "single" the calibrator only.
+    64 x 64 grid of 1 m cells, 2x2 kernel."""
+    s_lay, _, s_sky, _ = (_rng(k) for k in _streams(seed))
+    Na, N, dx = 51, 64, 1.0
+    ant = s_lay.uniform(-24.0, 24.0, size=(Na, 2))
+    freq = (140.0 + 20.0 * (np.arange(n_chan) + 0.5) / n_chan) * 1e6
+    x0 = _grid_for_disk(24.0 * np.sqrt(2.0), N, dx)
+    arr = ArraySpec(ant_xy=ant, freq_hz=freq, nx=N, ny=N, dx=dx, dy=dx, x0=x0, y0=x0, kernel=2, efmt=FMT_CF32)
+    lm = random_disk_lm(s_sky, 49, 0.5)
+    S = s_sky.uniform(0.2, 0.5, size=49)
+    src = np.concatenate([np.array([[0.0, 0.0, 5.0]]), np.column_stack([lm, S])])
+    mdl = src.copy() if model == "full" else src[:1].copy()
+    g = np.ones((n_chan, Na), np.complex128)
+    wl = Workload(name=f"noise_{model}", seed=seed, array=arr, src_lmS=src, model_lmS=mdl,
+                  cal_lm=np.array([0.0, 0.0]), g_true=g, g0=g.copy(), gamma=0.35, t_cal=t_cal,
+                  n_samples=t_cal * n_iter, sigma_r=sigma_r, quant_scale=1.0)
+    return wl.replace(**over) if over else wl
+
+
 def config_hera(seed: int = 3, n_chan: int = 512, n_samples: int = 2000, **over) -> Workload:
     """HERA shape: 350 antennas on a 14 m hexagonal lattice, 8+8-bit E-fields,
     channels across 100-200 MHz, 128x128 grid of 2.5 m cells (origin offset a

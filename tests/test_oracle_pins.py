@@ -663,3 +663,88 @@ def test_band_fit_skips_zero_solutions():
     s[3, 1] = 0.0
     mean, _ = O.band_fit(s, ok, x, "mean")
     assert abs(mean[0, 1] - s[:, 1].mean()) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# the visibility-based comparison calibrator and sigma_g (Sec. 4)
+# ---------------------------------------------------------------------------
+
+def _vis_case(Na=9, n_src=4, seed=12):
+    rng = np.random.default_rng(seed)
+    ant = rng.uniform(-20, 20, (Na, 2))
+    sky = np.column_stack([rng.uniform(-0.3, 0.3, (n_src, 2)), rng.uniform(1, 5, n_src)])
+    VM = O.model_visibilities(ant, 150e6, sky)
+    g = (1 + 0.3 * crandn(Na, rng=rng)) * np.exp(1j * rng.uniform(-np.pi, np.pi, Na))
+    return rng, VM, g
+
+
+def test_visibilities_are_pair_correlations():
+    rng = np.random.default_rng(13)
+    E = crandn(40, 5, rng=rng)
+    V = O.visibilities(E)
+    for a in range(5):
+        for b in range(5):
+            assert abs(V[a, b] - np.mean(E[:, a] * np.conj(E[:, b]))) < 1e-14
+
+
+def test_vis_chi2_noiseless_recovers_gains():
+    """V_ab = g_a g_b* V^M_ab exactly: chi^2 reaches 0 and the gains come
+    back up to one global phase, from unit starting gains."""
+    rng, VM, g = _vis_case()
+    V = np.outer(g, np.conj(g)) * VM
+    got = O.vis_chi2_gains(V, VM, np.ones_like(g))
+    assert O.vis_chi2(V, VM, got) < 1e-20 * np.sum(np.abs(V) ** 2)
+    assert O.gain_error(got[None, :], g[None, :]) < 1e-10
+
+
+def test_vis_chi2_matches_a_general_least_squares_solver():
+    """Noisy visibilities: the alternating solution and scipy's trust-region
+    least squares on the real parameters reach the same minimum of eq.
+    (vis_cal) and the same gains up to a global phase."""
+    from scipy.optimize import least_squares
+    rng, VM, g = _vis_case(Na=7, n_src=3, seed=14)
+    N = 0.2 * crandn(7, 7, rng=rng)
+    V = np.outer(g, np.conj(g)) * VM + (N + N.conj().T) / 2
+    ours = O.vis_chi2_gains(V, VM, np.ones(7, complex))
+    off = ~np.eye(7, dtype=bool)
+
+    def resid(p):
+        gg = p[:7] + 1j * p[7:]
+        r = (V - np.outer(gg, np.conj(gg)) * VM)[off]
+        return np.concatenate([r.real, r.imag])
+    sol = least_squares(resid, np.concatenate([np.ones(7), np.zeros(7)]), xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    theirs = sol.x[:7] + 1j * sol.x[7:]
+    c_ours, c_theirs = O.vis_chi2(V, VM, ours), O.vis_chi2(V, VM, theirs)
+    assert abs(c_ours - c_theirs) <= 1e-9 * c_theirs
+    assert O.gain_error(ours[None, :], theirs[None, :]) < 1e-6
+
+
+def test_gain_error_closed_forms():
+    """eq. (gain_error): real relative errors eps give sqrt(mean eps^2); a
+    common phase per channel is not an error."""
+    rng = np.random.default_rng(15)
+    gt = crandn(3, 10, rng=rng) + 2
+    eps = rng.uniform(-0.1, 0.1, (3, 10))
+    assert abs(O.gain_error(gt * (1 + eps), gt) - np.sqrt(np.mean(eps ** 2))) < 1e-15
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 3))[:, None]
+    assert O.gain_error(gt * ph, gt) < 1e-15
+    assert abs(O.gain_error(gt * (1 + eps) * ph, gt) - np.sqrt(np.mean(eps ** 2))) < 1e-14
+
+
+def test_effective_time_golden():
+    """eq. (teff) against the value printed in Sec. 4."""
+    with open(os.path.join(GOLDEN, "teff.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        assert round(O.effective_time(1.0, case["gamma"]), case["digits"]) == case["printed"]
+
+
+def test_epical_gains_without_images_is_the_loop():
+    """The image-free recursion used by the noise study equals the imaged
+    loop (run_channel) interval by interval."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=2, n_ant=20, n_samples=120, t_cal=30)
+    pb = O.Problem.from_workload(wl)
+    for c in range(2):
+        E = synth.efield_channel(wl, c)
+        np.testing.assert_allclose(O.epical_gains(E, pb, c, wl.g0[c]), O.run_channel(E, pb, c, wl.g0[c])["gains"],
+                                   rtol=1e-11, atol=1e-13)

@@ -381,6 +381,31 @@ def run_channel(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, setup=None,
     return out
 
 
+def run_channel_snapshots(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, t_acc: int, setup=None):
+    """The calibrated loop of run_channel, imaged in windows: window w holds
+    the mean of |script-E'(t)|^2 over the samples w t_acc .. (w+1) t_acc - 1
+    (the last window may be short) instead of one mean over the run --
+    short-timescale images for transient science (Sec. 1).  The gains follow
+    the same recursion as run_channel.  Returns dict(images [n_win, ny, nx],
+    gains [n_int + 1, Na])."""
+    s = channel_setup(pb, ch) if setup is None else setup
+    cells, (kx0, ky0), A, D, na, flags = s["cells"], s["k0"], s["A"], s["D"], s["na"], s["flags"]
+    T = E.shape[0]
+    n_win = -(-T // t_acc)
+    sums = np.zeros((n_win, pb.ny, pb.nx), np.float64)
+    g = np.array(g0, np.complex128).copy()
+    hist = [g.copy()]
+    for (t0, t1) in intervals(T, pb.t_cal):
+        X = dft2(grid(calibrate(E[t0:t1], g, flags), cells, pb.nx, pb.ny), na)
+        for k in range(t1 - t0):
+            sums[(t0 + k) // t_acc] += np.abs(X[k]) ** 2
+        K, Q = correlate(np.where(flags == 0, E[t0:t1], 0.0), X[:, ky0, kx0])
+        g, _ = gain_update(K / (t1 - t0), Q / (t1 - t0), A, D, g, na, pb.gamma, flags)
+        hist.append(g.copy())
+    lens = np.array([min(t_acc, T - w * t_acc) for w in range(n_win)], np.float64)
+    return dict(images=sums / lens[:, None, None], gains=np.array(hist))
+
+
 def run_channel_multi(E: np.ndarray, pb: Problem, ch: int, g0: np.ndarray, setup=None):
     """The calibrated loop with several tapped pixels (gain_update_multi).
 

@@ -748,3 +748,35 @@ def test_epical_gains_without_images_is_the_loop():
         E = synth.efield_channel(wl, c)
         np.testing.assert_allclose(O.epical_gains(E, pb, c, wl.g0[c]), O.run_channel(E, pb, c, wl.g0[c])["gains"],
                                    rtol=1e-11, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# snapshot images (windows of t_acc samples)
+# ---------------------------------------------------------------------------
+
+def test_snapshots_one_window_is_the_run_image():
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=1, n_ant=16, n=16, n_samples=70, t_cal=20)
+    E = synth.efield_channel(wl, 0)
+    pb = O.Problem.from_workload(wl)
+    run = O.run_channel(E, pb, 0, wl.g0[0])
+    for t_acc in (70, 500):
+        snap = O.run_channel_snapshots(E, pb, 0, wl.g0[0], t_acc)
+        assert snap["images"].shape == (1, 16, 16)
+        np.testing.assert_allclose(snap["images"][0], run["image"], rtol=1e-13)
+        np.testing.assert_allclose(snap["gains"], run["gains"], rtol=1e-13)
+
+
+def test_snapshots_average_to_the_run_image_and_tap_power():
+    """Ragged windows: the length-weighted mean of the windows is the run
+    image; with t_acc = 1 the tapped pixel of each window is |P(t)|^2, P the
+    tap the loop correlates."""
+    wl = synth.config_small(efmt=synth.FMT_CF32, n_chan=1, n_ant=16, n=16, n_samples=73, t_cal=20)
+    E = synth.efield_channel(wl, 0)
+    pb = O.Problem.from_workload(wl)
+    run = O.run_channel(E, pb, 0, wl.g0[0], keep_taps=True)
+    snap = O.run_channel_snapshots(E, pb, 0, wl.g0[0], 10)
+    lens = np.array([10] * 7 + [3], float)
+    np.testing.assert_allclose(np.tensordot(lens, snap["images"], 1) / 73, run["image"], rtol=1e-12)
+    one = O.run_channel_snapshots(E, pb, 0, wl.g0[0], 1)
+    kx, ky = O.channel_setup(pb, 0)["k0"]
+    np.testing.assert_allclose(one["images"][:, ky, kx], np.abs(run["taps"]) ** 2, rtol=1e-12)

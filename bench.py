@@ -422,6 +422,89 @@ def bench_single(args, dev):
     return out
 
 
+def bench_snapshot(args, dev):
+    """Snapshot images (epic_run_snapshots): one image per window of t_acc
+    samples instead of one per run.  At t_acc = 1 every frame writes its own
+    16 KiB image, so HBM writes join the FP32 work as a bound."""
+    import torch
+    from paper_1603_02126_amd import lib
+    from oracle import epic_oracle as O
+    wl = workload(args.workload)
+    a = wl.array
+    t_acc = args.snapshot
+    T = wl.n_samples
+    n_win = -(-T // t_acc)
+    print(f"# generating {describe(wl)}; snapshots every {t_acc} samples", file=sys.stderr, flush=True)
+    packed = synth.make_efield(wl, threads=min(16, os.cpu_count() or 1))
+    plan = new_plan([wl])
+    e = torch.from_numpy(packed).to(dev)
+    g0 = torch.from_numpy(wl.g0).to(dev)
+    g = torch.empty_like(g0)
+    imgs = torch.empty((n_win, a.n_chan, a.ny, a.nx), dtype=torch.float32, device=dev)
+
+    def step():
+        g.copy_(g0)
+        plan.run_snapshots(0, e, T, t_acc, g, imgs)
+    dt, tim = Timer([plan])(step, args.steps, args.warmup)
+    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    frames = a.n_chan * T
+    ms_step = dt / args.steps * 1e3
+    img_ms, img_n = tim[lib.TIMER_IMAGE]
+    avg_img_ms = img_ms / max(1, img_n)
+    k2 = 1 if a.kernel == 1 else 4
+    bpe = synth.FMT_BYTES[a.efmt]
+    flops_launch = imaging_flops_per_frame(a.nx, a.n_ant, k2) * frames
+    bytes_frame = a.n_ant * bpe + 8.0 * a.n_ant / wl.t_cal + 4.0 * a.nx * a.ny / t_acc
+    bytes_launch = bytes_frame * frames
+    tflops = flops_launch / (avg_img_ms * 1e-3) / 1e12
+    gbs = bytes_launch / (avg_img_ms * 1e-3) / 1e9
+    hbm_bound = bytes_launch / (PEAK_HBM_GBS * 1e9) > flops_launch / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+    roof = ({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+            if hbm_bound else
+            {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+             "frac": tflops / PEAK_FP32_VECTOR_TFLOPS})
+    roof.update({"traffic": None, "algorithmic_bytes_per_launch": bytes_launch, "hbm_bytes_per_frame": bytes_frame,
+                 "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
+                 "hbm_frac": gbs / PEAK_HBM_GBS, "alu_frac": tflops / PEAK_FP32_VECTOR_TFLOPS,
+                 "kernel": "k_image_snap / k_image_pair_snap (calibrate+grid+FFT+|X|^2, one image per window)",
+                 "avg_launch_ms": avg_img_ms})
+    cpu, parity = None, None
+    if args.cpu_budget > 0:
+        print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        pb = O.Problem.from_workload(wl)
+        done, errs, gerrs, t_used = [], [], [], 0.0
+        ch = 0
+        gains = g.cpu().numpy()
+        while ch < a.n_chan and (not done or t_used < args.cpu_budget):
+            E = O.unpack(packed[:, ch], a.efmt)
+            t0 = time.perf_counter()
+            r = O.run_channel_snapshots(E, pb, ch, wl.g0[ch], t_acc)
+            t_used += time.perf_counter() - t0
+            got = imgs[:, ch].cpu().numpy()
+            errs.append(float((np.abs(got - r["images"]).reshape(n_win, -1).max(1) /
+                               np.abs(r["images"]).reshape(n_win, -1).max(1)).max()))
+            gerrs.append(gain_rel_err(gains[ch], r["gains"][-1]))
+            done.append(ch)
+            del r
+            ch += max(1, a.n_chan // 7)
+        fr = len(done) * T
+        cpu = {"value": fr / t_used, "unit": "frames/s", "cores": oracle_threads(), "kind": "oracle",
+               "sample": f"channels {done} x all {T} samples ({fr} frames, {t_used:.1f} s)"}
+        parity = {"channels": done, "max_window_image_rel_err": max(errs), "gain_rel_err": max(gerrs)}
+    out = base_record(args, frames / (dt / args.steps), ms_step, "f32", {
+        "workload": describe(wl) + f"; snapshot images every {t_acc} samples ({n_win} per channel)",
+        "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan, "grid": [a.ny, a.nx], "n_samples": T,
+        "t_cal": wl.t_cal, "t_acc": t_acc, "efmt": synth.FMT_NAMES[a.efmt], "path": "snapshot images",
+        "parallelism": "1 GPU"})
+    out.update({"roofline": roof,
+                "kernels": {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+                            "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps)},
+                "image_bytes_per_step": 4.0 * a.nx * a.ny * n_win * a.n_chan,
+                "cpu_baseline": cpu, "parity_vs_oracle": parity})
+    plan.close()
+    return out
+
+
 def bench_uneven(args, dev):
     """Eight arrays of uneven size: per-array launches (plain) against the
     batched persistent form in a hipGraph after autotuning."""
@@ -616,6 +699,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="time only the plain FP32 path")
     ap.add_argument("--pixels", type=int, default=1,
                     help="tapped pixels of EPICal (lwa/hera/tiny; > 1: calibrator plus brightest sources)")
+    ap.add_argument("--snapshot", type=int, default=0,
+                    help="t_acc > 0: time epic_run_snapshots (one image per t_acc samples) on lwa/tiny")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -628,7 +713,9 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.workload == "uneven":
+    if args.snapshot > 0:
+        out = bench_snapshot(args, dev)
+    elif args.workload == "uneven":
         out = bench_uneven(args, dev)
     elif args.workload == "diff":
         out = bench_diff(args, dev)

@@ -325,6 +325,24 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
              float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
              epic_stream_t stream);
 
+/* Snapshot images of one array: the calibrated loop of epic_run (the same
+ * calibration solve and gains) with one image per window of t_acc
+ * consecutive samples instead of one image over the run -- the short
+ * timescale images for transient science that motivate direct imaging
+ * (Sec. 1: output rate and millisecond events).
+ *   efield:    device [n_samples][F][Na] packed
+ *   gains:     device [F][Na] complex128; in: g^(0), out: g^(n_int)
+ *   images:    device [n_win][F][ny][nx] float32, n_win = ceil(n_samples / t_acc);
+ *              window w = mean of |X_t|^2 over t = w t_acc .. min((w+1) t_acc, n_samples) - 1
+ *              (the last window may be short), X_t as in epic_run
+ *   gain_hist, ant_status: as in epic_run (may be NULL)
+ * t_acc >= 1 (1: one image per sample).  Grids up to 64 x 64, FFT transform
+ * (EPIC_ERR_UNSUPPORTED otherwise); several tapped pixels and gains shared
+ * over a band apply as in epic_run. */
+int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, int64_t t_acc,
+                       double* gains, float* images, double* gain_hist, uint32_t* ant_status,
+                       epic_stream_t stream);
+
 /* Fixed-gain imaging of one array (the loop with calibration frozen):
  *   image[f] = (1/n_samples) sum_t |X_t|^2 with E'_a = E_a / g[f][a].
  * gains: device [F][Na] complex128.  image: device [F][ny][nx] float32. */

@@ -991,23 +991,72 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   return EPIC_OK;
 }
 
+// The calibration solve of one array in the per-array form: the cooperative
+// band solve when its channels share gains, else one workgroup per channel.
+static hipError_t solve_array(epic_plan_t plan, const ArrayPlan& ap, const epic::SolveArgs& sa, char* band_scr,
+                              hipStream_t s) {
+  if (ap.band_mode == EPIC_BAND_NONE) return epic::launch_solve(sa, s);
+  const HostArray& h = ap.h;
+  epic::BandArgs b{};
+  b.s = sa;
+  b.b0 = ap.band_b0;
+  b.b1 = ap.band_b1;
+  b.mode = ap.band_mode;
+  b.deg_amp = ap.band_deg_amp;
+  b.deg_phase = ap.band_deg_phase;
+  b.x = ap.d_band_x;
+  b.raw = reinterpret_cast<double2*>(band_scr);
+  b.coef = reinterpret_cast<double*>(band_scr + align256(size_t(h.F) * h.na * sizeof(double2)));
+  b.bar = reinterpret_cast<uint32_t*>(band_scr + align256(size_t(h.F) * h.na * sizeof(double2)) +
+                                      align256(size_t(h.na) * epic::kBandCoef * sizeof(double)));
+  return epic::launch_solve_band(b, plan->n_cu, s);
+}
+
+static epic::SolveArgs solve_args(const ArrayPlan& ap, const RunLayout& lay, char* scr, const void* efield,
+                                  int64_t n_samples, double* gains, double* gain_hist, uint32_t* status) {
+  const HostArray& h = ap.h;
+  epic::SolveArgs sa{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, ap.t_cal, int(lay.n_int),
+                     ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma, reinterpret_cast<double2*>(gains),
+                     reinterpret_cast<float2*>(scr + lay.u_off),
+                     gain_hist ? reinterpret_cast<double2*>(gain_hist)
+                               : reinterpret_cast<double2*>(scr + lay.gh_off),
+                     status};
+  sa.n_pix = ap.n_pix;
+  return sa;
+}
+
+// Scratch of one array's run, appended at `need`: u history, partial images
+// (`partials` floats per split), gain history, band scratch.
+static int layout_array(const ArrayPlan& ap, int64_t n_samples, int splits, size_t partials, RunLayout& lay,
+                        size_t& need, bool& any_band) {
+  lay.n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
+  if (lay.n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
+  lay.splits = splits;
+  lay.u_off = need;
+  need += align256(size_t(lay.n_int) * ap.h.F * ap.h.na * sizeof(float2));
+  lay.p_off = need;
+  need += align256(size_t(splits) * partials * sizeof(float));
+  lay.gh_off = need;
+  need += align256(size_t(lay.n_int + 1) * ap.h.F * ap.h.na * sizeof(double2));
+  lay.band_off = need;
+  if (ap.band_mode != EPIC_BAND_NONE) {
+    if (ap.n_pix != 1) return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band take one tapped pixel");
+    any_band = true;
+    need += align256(size_t(ap.h.F) * ap.h.na * sizeof(double2)) +
+            align256(size_t(ap.h.na) * epic::kBandCoef * sizeof(double)) + 256;
+  }
+  return EPIC_OK;
+}
+
 // Enqueue the whole run on `s`; batched selects the one-launch-per-stage form.
 static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char* scr, const void* const* efield,
                        int64_t n_samples, double* const* gains, float* const* image, double* const* gain_hist,
                        uint32_t* const* ant_status, hipStream_t s, bool batched, bool timed) {
   const int na_arr = int(plan->arrays.size());
   std::vector<epic::SolveArgs> sa(na_arr);
-  for (int i = 0; i < na_arr; ++i) {
-    ArrayPlan& ap = plan->arrays[i];
-    const HostArray& h = ap.h;
-    sa[i] = epic::SolveArgs{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt, ap.t_cal,
-                            int(lay[i].n_int), ap.d_A, ap.d_D, ap.d_hold, double(h.na_eff), ap.gamma,
-                            reinterpret_cast<double2*>(gains[i]), reinterpret_cast<float2*>(scr + lay[i].u_off),
-                            gain_hist ? reinterpret_cast<double2*>(gain_hist[i])
-                                      : reinterpret_cast<double2*>(scr + lay[i].gh_off),
-                            ant_status ? ant_status[i] : nullptr};
-    sa[i].n_pix = ap.n_pix;
-  }
+  for (int i = 0; i < na_arr; ++i)
+    sa[i] = solve_args(plan->arrays[i], lay[i], scr, efield[i], n_samples, gains[i],
+                       gain_hist ? gain_hist[i] : nullptr, ant_status ? ant_status[i] : nullptr);
   // FP32 u of every interval from the gain history the solve wrote
   auto hist_to_u = [&](int i) -> hipError_t {
     const HostArray& h = plan->arrays[i].h;
@@ -1018,26 +1067,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       ArrayPlan& ap = plan->arrays[i];
       {
         Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
-        hipError_t e;
-        if (ap.band_mode != EPIC_BAND_NONE) {
-          const HostArray& h = ap.h;
-          char* bp = scr + lay[i].band_off;
-          epic::BandArgs b{};
-          b.s = sa[i];
-          b.b0 = ap.band_b0;
-          b.b1 = ap.band_b1;
-          b.mode = ap.band_mode;
-          b.deg_amp = ap.band_deg_amp;
-          b.deg_phase = ap.band_deg_phase;
-          b.x = ap.d_band_x;
-          b.raw = reinterpret_cast<double2*>(bp);
-          b.coef = reinterpret_cast<double*>(bp + align256(size_t(h.F) * h.na * sizeof(double2)));
-          b.bar = reinterpret_cast<uint32_t*>(bp + align256(size_t(h.F) * h.na * sizeof(double2)) +
-                                              align256(size_t(h.na) * epic::kBandCoef * sizeof(double)));
-          e = epic::launch_solve_band(b, plan->n_cu, s);
-        } else {
-          e = epic::launch_solve(sa[i], s);
-        }
+        hipError_t e = solve_array(plan, ap, sa[i], scr + lay[i].band_off, s);
         if (e == hipSuccess) e = hist_to_u(i);
         if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
       }
@@ -1136,22 +1166,9 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     if (!epic::solve_supported(ap.h.na, ap.h.efmt, ap.n_pix))
       return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
-    lay[i].n_int = (n_samples + ap.t_cal - 1) / ap.t_cal;
-    if (lay[i].n_int > std::numeric_limits<int>::max()) return fail(EPIC_ERR_ARG, "too many calibration intervals");
-    lay[i].splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
-    lay[i].u_off = need;
-    need += align256(size_t(lay[i].n_int) * ap.h.F * ap.h.na * sizeof(float2));
-    lay[i].p_off = need;
-    need += align256(size_t(lay[i].splits) * ap.h.F * ap.h.nx * ap.h.ny * sizeof(float));
-    lay[i].gh_off = need;
-    need += align256(size_t(lay[i].n_int + 1) * ap.h.F * ap.h.na * sizeof(double2));
-    lay[i].band_off = need;
-    if (ap.band_mode != EPIC_BAND_NONE) {
-      if (ap.n_pix != 1) return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band take one tapped pixel");
-      any_band = true;
-      need += align256(size_t(ap.h.F) * ap.h.na * sizeof(double2)) +
-              align256(size_t(ap.h.na) * epic::kBandCoef * sizeof(double)) + 256;
-    }
+    rc = layout_array(ap, n_samples, pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits),
+                      size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
+    if (rc) return rc;
     all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
   if (any_band && plan->batch == 1)
@@ -1228,6 +1245,49 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   e = hipEventRecord(plan->ev_out, plan->gstream);
   if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->ev_out, 0);
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "graph stream ordering");
+}
+
+int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, int64_t t_acc,
+                       double* gains, float* images, double* gain_hist, uint32_t* ant_status, epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", array);
+  if ((rc = check_grid_supported(ap))) return rc;
+  if (ap.h.nx > 64) return fail(EPIC_ERR_UNSUPPORTED, "snapshot images support grids up to 64 x 64 (got %d)", ap.h.nx);
+  if (!epic::solve_supported(ap.h.na, ap.h.efmt, ap.n_pix))
+    return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  if (t_acc < 1) return fail(EPIC_ERR_ARG, "t_acc must be >= 1");
+  if (!efield || !gains || !images) return fail(EPIC_ERR_ARG, "efield, gains and images must not be NULL");
+  const int64_t n_win = (n_samples + t_acc - 1) / t_acc;
+  // every split holds at least one window; the splits fill the chip as in epic_run
+  int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
+  splits = int(std::min<int64_t>(splits, std::max<int64_t>(1, n_win / slots_for(ap.h.nx))));
+  RunLayout lay{};
+  size_t need = 0;
+  bool any_band = false;
+  if ((rc = layout_array(ap, n_samples, splits, 0, lay, need, any_band))) return rc;
+  void* scr = nullptr;
+  if ((rc = scratch(plan, need, &scr))) return rc;
+  char* sc = static_cast<char*>(scr);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const HostArray& h = ap.h;
+  const epic::SolveArgs sa = solve_args(ap, lay, sc, efield, n_samples, gains, gain_hist, ant_status);
+  {
+    Timed tm(plan, EPIC_TIMER_SOLVE, s, true);
+    hipError_t e = solve_array(plan, ap, sa, sc + lay.band_off, s);
+    if (e == hipSuccess) e = epic::launch_hist_to_u(sa.g_hist, ap.d_hold, lay.n_int, h.F, h.na, sa.u_hist, s);
+    if (e != hipSuccess) return hip_fail(e, "calibration solve launch");
+  }
+  ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, sa.u_hist, ap.t_cal, ap.d_slots,
+               ap.n_slots, splits, nullptr, ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
+  ia.t_acc = t_acc;
+  ia.snap = images;
+  ia.snap_scale = 1.0 / (double(h.na_eff) * double(h.na_eff));
+  Timed tm(plan, EPIC_TIMER_IMAGE, s, true);
+  hipError_t e = epic::launch_image_snap(h.nx, ia, s);
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "snapshot imaging launch");
 }
 
 int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, const double* gains,

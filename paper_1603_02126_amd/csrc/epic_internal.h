@@ -32,6 +32,12 @@ struct ImageArgs {
   // null when not built
   const uint2* slots_h = nullptr;
   int n_slots_h0 = 0, n_slots_h1 = 0;
+  // snapshot form: one image per window of t_acc samples, written to
+  // snap[window][F][N*N] scaled by snap_scale / (samples in the window);
+  // splits then divide the windows of a channel (0: whole-run average)
+  int64_t t_acc = 0;
+  float* snap = nullptr;
+  double snap_scale = 0.0;
 };
 
 // Stage-wise gridding to HBM.
@@ -174,6 +180,8 @@ bool pair_engine(const ImageArgs& a, int N);   // the 64 x 64 two-waves-per-SIMD
 bool dft_supported(int N, int na, int n_slots);
 hipError_t launch_image_dft(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);
+// snapshot form (a.t_acc >= 1, a.snap set; N <= 64)
+hipError_t launch_image_snap(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);
 hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,

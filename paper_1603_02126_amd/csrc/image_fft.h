@@ -213,3 +213,171 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
 }
 
 }  // namespace epic
+
+namespace epic {
+
+// ---------------------------------------------------------------------------
+// Snapshot forms of the two N <= 64 engines: one image per window of t_acc
+// consecutive samples (the short-timescale images of transient science)
+// instead of the average over the run.  The windows of a channel are split
+// over the workgroups; each frame slot (a lane group of the one-wave engine,
+// a wave of the paired engine) takes whole windows in turn, accumulates their
+// frames in registers and stores the window's image itself: no reduction
+// between slots, no atomics, and every store writes a row of N contiguous
+// pixels.
+// ---------------------------------------------------------------------------
+
+// Walks one slot's frames: windows j = j0, j0 + stride, ... below j_end
+// (j_end <= the number of windows), the samples of each window in order (the
+// last window of the run may be short).  `valid`: the cursor is on a sample;
+// `last`: that sample ends its window.
+struct SnapCursor {
+  int64_t j, i, j_end, stride, t_acc, n_t;
+  __device__ __forceinline__ int64_t t() const { return j * t_acc + i; }
+  __device__ __forceinline__ int64_t len() const { return min(t_acc, n_t - j * t_acc); }
+  __device__ __forceinline__ bool valid() const { return j < j_end; }
+  __device__ __forceinline__ bool last() const { return i == len() - 1; }
+  __device__ __forceinline__ void next() {
+    if (++i >= len()) {
+      i = 0;
+      j += stride;
+    }
+  }
+};
+
+template <int N>
+__device__ __forceinline__ void snap_store(const ImageArgs& a, int f, int64_t j, float (&acc)[N], int lam) {
+  const int64_t len = min(a.t_acc, a.n_t - j * a.t_acc);
+  const float sc = float(a.snap_scale / double(len));
+  float* out = a.snap + (j * a.F + f) * int64_t(N * N);
+  static_for<0, N>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    out[y * N + lam] = acc[y] * sc;
+    acc[y] = 0.f;
+  });
+}
+
+template <int N, int APL>
+__device__ __forceinline__ void image_item_snap(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  using G = Geo<N>;
+  float2* lds = reinterpret_cast<float2*>(smem);
+  float2* lds_e = reinterpret_cast<float2*>(smem + FftSmem<N, APL>::E_OFF);
+  uint2* stab = reinterpret_cast<uint2*>(smem + FftSmem<N, APL>::T_OFF);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane / N, lam = lane % N;
+  const int slot = wave * G::FPW + h;
+  const int64_t W = (a.n_t + a.t_acc - 1) / a.t_acc;
+  const int64_t wb = W * s / a.splits, we = W * (s + 1) / a.splits;
+  float2* buf = lds + slot * G::FRAME;
+  float2* epr = lds_e + slot * (APL * N);
+
+  load_slot_table(stab, a.slots, a.n_slots, N);
+  static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  __syncthreads();
+
+  float acc[N];
+  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  // every slot walks the same number of steps (the slots of one wave stay in
+  // step; frames past a slot's windows are empty)
+  const int64_t steps = (we - wb + G::SLOTS - 1) / G::SLOTS * a.t_acc;
+  SnapCursor cur{wb + slot, 0, we, G::SLOTS, a.t_acc, a.n_t};
+  SnapCursor nxt = cur;
+  Raw raw[APL];
+  float2 uu[APL];
+  fetch_frame<N, APL>(raw, uu, a.efield, a.u, cur.t(), a.t_cal, f, a.F, a.Na, a.fmt, lam, cur.valid());
+  for (int64_t q = 0; q < steps; ++q) {
+    stage_frame<N, APL>(epr, raw, uu, lam, a.Na, a.fmt, cur.valid());
+    nxt.next();
+    fetch_frame<N, APL>(raw, uu, a.efield, a.u, nxt.t(), a.t_cal, f, a.F, a.Na, a.fmt, lam, nxt.valid());
+    wave_lds_sync();
+    grid_frame(buf, epr, stab, a.n_slots, N, lam);
+    wave_lds_sync();
+    float2 v[N];
+    transform_frame<N, +1>(buf, v, lam);
+    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    if (cur.valid() && cur.last()) snap_store<N>(a, f, cur.j, acc, lam);
+    cur = nxt;
+  }
+  __syncthreads();
+}
+
+template <int APL, int FMT>
+__device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
+  constexpr int N = 64, P = Geo<64>::PITCH, INFLIGHT = 8;
+  using L = PairSmem<APL>;
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float2* H = lds + wave * L::WAVE;
+  float2* epr = H + L::HALF;
+  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
+  const int S0 = a.n_slots_h0, S1 = a.n_slots_h1;
+  const int64_t W = (a.n_t + a.t_acc - 1) / a.t_acc;
+  const int64_t wb = W * s / a.splits, we = W * (s + 1) / a.splits;
+
+  load_slot_table(stab, a.slots_h, S0 + S1, N);
+  if (lam < 32) static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  __syncthreads();
+
+  float acc[N];
+  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  float2 v[N];
+  uint32_t raw[APL];
+  constexpr int bpe = FMT == kCI4 ? 1 : 2;
+  auto fetch_raw = [&](const SnapCursor& c) {
+    const bool ok = c.valid();
+    const uint8_t* row = a.efield + (c.t() * a.F + f) * int64_t(a.Na) * bpe;
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      raw[decltype(ic)::value] = (ok && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
+    });
+  };
+  // the waves are independent: each walks its own windows
+  SnapCursor cur{wb + wave, 0, we, INFLIGHT, a.t_acc, a.n_t};
+  fetch_raw(cur);
+  while (cur.valid()) {
+    const int64_t t = cur.t();
+    __builtin_amdgcn_s_setprio(1);
+    const float2* urow = a.u + ((t / a.t_cal) * a.F + f) * int64_t(a.Na);
+    float2 uu[APL];
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+    });
+    static_for<0, APL>([&](auto ic) {
+      const int an = lam + N * decltype(ic)::value;
+      if (an < a.Na) epr[an] = cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, FMT), uu[decltype(ic)::value]);
+    });
+    wave_lds_sync();
+    grid_frame<8>(H, epr, stab, S0, N, lam);
+    wave_lds_sync();
+    if (lam < 32) {
+      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
+      static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    wave_lds_sync();
+    grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
+    wave_lds_sync();
+    if (lam >= 32) {
+      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
+      static_for<0, N>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+    }
+    wave_lds_sync();
+    __builtin_amdgcn_s_setprio(0);
+    fft_reg<N, +1>(v);
+    __builtin_amdgcn_s_setprio(1);
+    transpose64(v, H, lam);
+    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    __builtin_amdgcn_s_setprio(0);
+    fft_reg<N, +1>(v);
+    SnapCursor nxt = cur;
+    nxt.next();
+    fetch_raw(nxt);
+    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    if (cur.last()) snap_store<N>(a, f, cur.j, acc, lam);
+    cur = nxt;
+  }
+  __syncthreads();
+}
+
+}  // namespace epic

@@ -45,6 +45,20 @@ __global__ __launch_bounds__(kPairThreads) void k_image_pair(ImageArgs a) {
   image_item_pair<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
+// Snapshot forms (one image per window of t_acc samples).
+template <int N, int APL>
+__global__ __launch_bounds__(256) void k_image_snap(ImageArgs a) {
+  __shared__ __align__(16) uint8_t smem[FftSmem<N, APL>::BYTES];
+  image_item_snap<N, APL>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
+}
+
+template <int APL, int FMT>
+__global__ __launch_bounds__(kPairThreads) void k_image_pair_snap(ImageArgs a) {
+  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
+  image_item_pair_snap<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_image_cls(ImageArgs a) {
   __shared__ __align__(16) uint8_t smem[ClsSmem<R, false>::BYTES];
@@ -243,6 +257,26 @@ hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   return dispatch_n<LaunchImage>(N, a.Na, a, s);
+}
+
+template <int N, int APL>
+struct LaunchImageSnap {
+  static hipError_t run(const ImageArgs& a, hipStream_t s) {
+    if constexpr (N == 64 && APL == 4) {
+      if (pair_engine(a, N)) {
+        if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair_snap<APL, kCI4>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_image_pair_snap<APL, kCI8>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_image_snap<N, APL>), dim3(a.F * a.splits), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_image_snap(int N, const ImageArgs& a, hipStream_t s) {
+  if (N > 64 || a.t_acc < 1 || !a.snap || a.splits < 1) return hipErrorInvalidValue;
+  return dispatch_n<LaunchImageSnap>(N, a.Na, a, s);
 }
 
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s) {

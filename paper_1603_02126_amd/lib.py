@@ -80,6 +80,9 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "epic_run_snapshots": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "epic_image": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_image_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
@@ -406,6 +409,28 @@ class Plan:
         a_s = VP(*ps) if status is not None else None
         keep += [a_e, a_g, a_i, a_h, a_s]
         _check(load().epic_run(self._h, a_e, int(n_samples), a_g, a_i, a_h, a_s, _stream(stream)))
+
+    def run_snapshots(self, i, efield, n_samples, t_acc, gains, images, gain_hist=None, status=None, stream=None):
+        """epic_run_snapshots: images [ceil(n_samples / t_acc), F, ny, nx] float32, one per window."""
+        torch = _torch()
+        F, Na, ny, nx = self._dims(i)
+        pe, T = self._efield(i, efield)
+        if T < n_samples:
+            raise ValueError("n_samples exceeds the E-field stream")
+        n_win = -(-int(n_samples) // int(t_acc)) if t_acc > 0 else 0
+        pg = _req(gains, torch.complex128, (F, Na), "gains", self.device)
+        pi = _req(images, torch.float32, (n_win, F, ny, nx), "images", self.device)
+        ph = ps = None
+        if gain_hist is not None:
+            m = self._models[i]
+            if m is None:
+                raise RuntimeError("set_model first")
+            n_int = -(-int(n_samples) // int(m.desc.t_cal))
+            ph = _req(gain_hist, torch.complex128, (n_int + 1, F, Na), "gain_hist", self.device)
+        if status is not None:
+            ps = _req(status, torch.int32, (F, Na), "status", self.device)
+        _check(load().epic_run_snapshots(self._h, int(i), pe, int(n_samples), int(t_acc), pg, pi, ph, ps,
+                                         _stream(stream)))
 
     def image(self, i, efield, n_samples, gains, out=None, stream=None):
         """epic_image: time-averaged image with fixed gains [F, Na] complex128."""

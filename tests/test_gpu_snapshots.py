@@ -1,0 +1,101 @@
+"""GPU parity of snapshot images (epic_run_snapshots: one image per window of
+t_acc samples along the calibrated loop) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import epic_oracle as O
+from paper_1603_02126_amd import synth
+
+from ._helpers import GAIN_RTOL, IMAGE_RTOL, gain_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_snap(wl, packed, t_acc, device, plan=None):
+    import torch
+    from paper_1603_02126_amd import lib
+    own = plan is None
+    if own:
+        plan = lib.Plan([wl.array])
+        plan.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
+    a = wl.array
+    n_win = -(-wl.n_samples // t_acc)
+    n_int = -(-wl.n_samples // wl.t_cal)
+    e = torch.from_numpy(np.ascontiguousarray(packed)).to(device)
+    g = torch.from_numpy(np.ascontiguousarray(wl.g0)).to(device)
+    imgs = torch.full((n_win, a.n_chan, a.ny, a.nx), -1.0, dtype=torch.float32, device=device)
+    gh = torch.zeros((n_int + 1, a.n_chan, a.n_ant), dtype=torch.complex128, device=device)
+    plan.run_snapshots(0, e, wl.n_samples, t_acc, g, imgs, gain_hist=gh)
+    torch.cuda.synchronize()
+    if own:
+        plan.close()
+    return imgs.cpu().numpy(), gh.cpu().numpy()
+
+
+def _oracle_snap(wl, packed, t_acc):
+    E = O.unpack(packed, wl.array.efmt)
+    pb = O.Problem.from_workload(wl)
+    res = [O.run_channel_snapshots(E[:, c], pb, c, wl.g0[c], t_acc) for c in range(wl.array.n_chan)]
+    return np.stack([r["images"] for r in res], axis=1), np.stack([r["gains"] for r in res], axis=1)
+
+
+def _window_err(got, ref):
+    """max over windows and channels of max|dI| / max|I|."""
+    d = np.abs(got - ref).reshape(got.shape[0], got.shape[1], -1).max(-1)
+    m = np.abs(ref).reshape(ref.shape[0], ref.shape[1], -1).max(-1)
+    return float((d / m).max())
+
+
+@pytest.mark.parametrize("n,efmt,kernel,na,n_chan,n_samples,t_cal,t_acc", [
+    (64, synth.FMT_CI4, 2, 200, 2, 150, 50, 1),     # paired engine, one image per sample
+    (64, synth.FMT_CI8, 2, 180, 2, 301, 100, 7),    # paired engine, ragged last window
+    (32, synth.FMT_CI8, 2, 48, 3, 230, 50, 10),     # one-wave engine, two frames per wave
+    (16, synth.FMT_CF32, 1, 30, 2, 64, 7, 64),      # one window
+    (16, synth.FMT_CF32, 1, 30, 2, 64, 7, 100),     # a window longer than the run
+    (64, synth.FMT_CF32, 2, 100, 2, 90, 30, 4),     # one-wave engine at 64 x 64
+])
+def test_snapshots_match_oracle(cuda, n, efmt, kernel, na, n_chan, n_samples, t_cal, t_acc):
+    wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_chan=n_chan, n_samples=n_samples,
+                            t_cal=t_cal)
+    packed = synth.make_efield(wl)
+    print(f"snapshots N={n} Na={na} F={n_chan} T={n_samples} t_acc={t_acc}", flush=True)
+    got, gh = _gpu_snap(wl, packed, t_acc, cuda)
+    ref, rg = _oracle_snap(wl, packed, t_acc)
+    assert got.shape == ref.shape
+    assert gain_err(gh, rg) <= GAIN_RTOL
+    assert _window_err(got, ref) <= IMAGE_RTOL
+
+
+def test_snapshots_average_to_the_run_image(cuda):
+    """The length-weighted mean of the windows equals epic_run's image."""
+    from ._helpers import gpu_run, image_err
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, n_ant=220, n_chan=3, n_samples=403, t_cal=100)
+    packed = synth.make_efield(wl)
+    got, _ = _gpu_snap(wl, packed, 25, cuda)
+    lens = np.array([25] * 16 + [3], float)
+    mean = np.tensordot(lens, got.astype(np.float64), 1) / 403
+    run = gpu_run(wl, packed, cuda)
+    assert image_err(mean, run["image"]).max() <= 1e-5
+
+
+def test_snapshot_errors(cuda):
+    import torch
+    from paper_1603_02126_amd import lib
+    wl = synth.config_small(n=32, n_chan=1, n_samples=20, t_cal=10)
+    plan = lib.Plan([wl.array])
+    plan.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
+    e = torch.from_numpy(synth.make_efield(wl)).to(cuda)
+    g = torch.ones((1, wl.array.n_ant), dtype=torch.complex128, device=cuda)
+    imgs = torch.zeros((20, 1, 32, 32), dtype=torch.float32, device=cuda)
+    with pytest.raises((lib.EpicError, ValueError)):
+        plan.run_snapshots(0, e, 20, 0, g, imgs)
+    plan.close()
+    big = synth.config_small(n=128, n_chan=1, n_samples=20, t_cal=10)
+    plan = lib.Plan([big.array])
+    plan.set_model(0, big.model_lmS, big.cal_lm, big.gamma, big.t_cal)
+    e = torch.from_numpy(synth.make_efield(big)).to(cuda)
+    g = torch.ones((1, big.array.n_ant), dtype=torch.complex128, device=cuda)
+    imgs = torch.zeros((20, 1, 128, 128), dtype=torch.float32, device=cuda)
+    with pytest.raises(lib.EpicError):
+        plan.run_snapshots(0, e, 20, 1, g, imgs)
+    plan.close()

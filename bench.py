@@ -43,15 +43,18 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published dense FP32 vector peak
 PEAK_FP16_MFMA_TFLOPS = 2500.0    # MI355X published dense FP16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the imaging kernel on the LWA-shaped workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by
-# what the same counter reads for a plain 256 MiB device copy (FETCH x2.000,
-# WRITE x1.000).  Valid only for the kernel sources they were taken on: any change
-# to those files makes the figure stale and it is reported as null.
-TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "engine.h", "fft_reg.h", "epic_internal.h", "epic_api.hip")
+# HBM bytes per launch of the imaging kernel on the LWA-shaped workload (averaged
+# and snapshot forms), from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
+# per dispatch), each scaled by what the same counter reads for a plain 256 MiB
+# device copy (FETCH x2.000, WRITE x1.000).  Valid only for the sources that
+# determine the imaging kernels' code, as they were when the counters were taken:
+# any change to one of them makes the figure stale and it is reported as null.
+TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "bb567ff9d0024b521b909f30a63b48c31f6c444cd93c29e12b4443b200078ade",
-            "fetch_kib": 177014.0, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "f62fdcbc75c5cdbc33577a5c4811f67070577a3f66ca762dc4f2894117452b59",
+            "fetch_kib": 177013.3, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "f62fdcbc75c5cdbc33577a5c4811f67070577a3f66ca762dc4f2894117452b59",
+                      "fetch_kib": 239783.0, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
 }
 
 
@@ -463,11 +466,15 @@ def bench_snapshot(args, dev):
             if hbm_bound else
             {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
              "frac": tflops / PEAK_FP32_VECTOR_TFLOPS})
-    roof.update({"traffic": None, "algorithmic_bytes_per_launch": bytes_launch, "hbm_bytes_per_frame": bytes_frame,
+    roof.update({"traffic": measured_traffic(f"{args.workload}_snapshot{t_acc}"),
+                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                 "algorithmic_bytes_per_launch": bytes_launch, "hbm_bytes_per_frame": bytes_frame,
                  "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
                  "hbm_frac": gbs / PEAK_HBM_GBS, "alu_frac": tflops / PEAK_FP32_VECTOR_TFLOPS,
                  "kernel": "k_image_snap / k_image_pair_snap (calibrate+grid+FFT+|X|^2, one image per window)",
                  "avg_launch_ms": avg_img_ms})
+    if args.copy_calib:
+        copy_reference(dev)
     cpu, parity = None, None
     if args.cpu_budget > 0:
         print("# timing the FP64 oracle on the host", file=sys.stderr, flush=True)

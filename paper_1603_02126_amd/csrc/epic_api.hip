@@ -1043,7 +1043,7 @@ static int layout_array(const ArrayPlan& ap, int64_t n_samples, int splits, size
     if (ap.n_pix != 1) return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band take one tapped pixel");
     any_band = true;
     need += align256(size_t(ap.h.F) * ap.h.na * sizeof(double2)) +
-            align256(size_t(ap.h.na) * epic::kBandCoef * sizeof(double)) + 256;
+            align256(size_t(ap.h.na) * epic::kBandCoef * sizeof(double)) + align256(256 * sizeof(uint32_t));
   }
   return EPIC_OK;
 }

@@ -94,7 +94,7 @@ struct BandArgs {
   const double* x;          // [F] band coordinate in [-1, 1] (band channels)
   double2* raw;             // [F][Na] undamped solutions of the current interval (NaN: none)
   double* coef;             // [Na][kBandCoef] band model of the current interval
-  uint32_t* bar;            // grid barrier counter, zero at launch
+  uint32_t* bar;            // grid barrier flags, one per workgroup (256), zero at launch
 };
 
 // Stage-wise EPICal accumulate / finalize.

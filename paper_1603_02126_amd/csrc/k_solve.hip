@@ -112,18 +112,16 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_band(BandArgs b) {
   __shared__ __align__(16) uint8_t smem[BandSmem::BYTES];
   __shared__ int s_ok;
   const SolveArgs& a = b.s;
-  const int G = gridDim.x, wave = threadIdx.x >> 6;
-  uint32_t target = 0;
+  const int G = gridDim.x;
+  uint32_t epoch = 0;
   for (int n = 0; n < a.n_int; ++n) {
     for (int f = blockIdx.x; f < a.F; f += G) band_interval<PS, FMT>(b, f, n, smem);
-    target += uint32_t(G);
-    if (!grid_barrier(b.bar, target, &s_ok)) {
+    if (!grid_barrier(b.bar, ++epoch, &s_ok)) {
       band_abort(b);
       return;
     }
-    for (int ant = wave * G + blockIdx.x; ant < a.Na; ant += (kSolveThreads / 64) * G) band_fit_antenna(b, ant);
-    target += uint32_t(G);
-    if (!grid_barrier(b.bar, target, &s_ok)) {
+    band_fit_phase(b);
+    if (!grid_barrier(b.bar, ++epoch, &s_ok)) {
       band_abort(b);
       return;
     }
@@ -160,9 +158,9 @@ hipError_t launch_solve_band(const BandArgs& b, int n_cu, hipStream_t s, int* gr
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
-  const int G = std::min(a.F, per_cu * n_cu);
+  const int G = std::min({a.F, per_cu * n_cu, kBandMaxGroups});
   if (groups) *groups = G;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, b.bar, 1);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBandMaxGroups), 0, s, b.bar, kBandMaxGroups);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   BandArgs arg = b;

@@ -36,28 +36,41 @@ __device__ __forceinline__ double2 get_shared2(const double2* p) {
   return make_double2(get_shared(&p->x), get_shared(&p->y));
 }
 
-// Grid-wide barrier of a cooperative launch (every workgroup resident).
-// Every wave first waits until its own memory operations have completed
-// (so its shared-data stores are visible at agent scope), then one lane per
-// workgroup arrives on the counter and polls it.  The poll is bounded: a
-// barrier that does not complete within kBandSpinLimit polls returns false
-// (the caller then stops), so every wave exits.
-__device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target, int* s_ok) {
+// Grid-wide barrier of a cooperative launch (every workgroup resident), on
+// one flag per workgroup: the barrier of epoch e is passed when every flag
+// holds e or more.  Every wave first waits until its own memory operations
+// have completed (so its shared-data stores are visible at agent scope),
+// then lane 0 stores the workgroup's flag and the first wave polls all flags
+// with a few wide loads.  Flags only grow, so they are never reset within a
+// launch; no workgroup waits on one shared counter (same-address atomics
+// from every workgroup are serialised by the memory system).  The poll is
+// bounded: a barrier that does not complete within kBandSpinLimit polls
+// returns false (the caller then stops), so every wave exits.
+constexpr int kBandMaxGroups = 256;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t epoch, int* s_ok) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, G = gridDim.x;
+    if (lane == 0) __hip_atomic_store(flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t polls = 0;
-    int ok = 1;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++polls >= kBandSpinLimit) {
-        ok = 0;
-        break;
+    bool done = false;
+    while (!done) {
+      bool mine = true;
+#pragma unroll
+      for (int k = 0; k < kBandMaxGroups / 64; ++k) {
+        const int w = lane + 64 * k;
+        if (w < G) mine = mine && __hip_atomic_load(flags + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      }
+      done = __all(mine);
+      if (!done) {
+        if (++polls >= kBandSpinLimit) break;
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    *s_ok = ok;
+    if (lane == 0) *s_ok = done ? 1 : 0;
   }
   __syncthreads();
   return *s_ok != 0;
@@ -319,6 +332,12 @@ __device__ __noinline__ void band_fit_antenna(const BandArgs& b, int ant) {
       put_shared(out + kBandMaxDeg + 1 + k, cp[k]);
     }
   }
+}
+
+// Phase 2 for one workgroup: the band model of the antennas its waves own.
+__device__ __noinline__ void band_fit_phase(const BandArgs& b) {
+  const int G = gridDim.x, wave = threadIdx.x >> 6;
+  for (int ant = wave * G + blockIdx.x; ant < b.s.Na; ant += (kSolveThreads / 64) * G) band_fit_antenna(b, ant);
 }
 
 // Phase 3: the damped update of one channel (eq. damping) towards the band

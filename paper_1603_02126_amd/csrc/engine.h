@@ -10,12 +10,46 @@ namespace epic {
 // small device helpers
 // ---------------------------------------------------------------------------
 
+// Global memory accesses with the address space stated.  Where a pointer
+// reaches the code through a function boundary (the batched kernel calls the
+// engines as functions) the compiler cannot tell that it points to global
+// memory and would use FLAT instructions, which also count against the LDS
+// wait counter: every LDS wait would then wait for the next frame's
+// prefetch as well.
+typedef unsigned int gvec2 __attribute__((ext_vector_type(2)));
+typedef unsigned int gvec4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  // vector structs (float2, uint2, ...) go through a native vector type: their
+  // copy constructor would take the address back to a generic pointer
+  if constexpr (sizeof(T) == 8 && alignof(T) >= 8) {
+    const gvec2 v = *(const __attribute__((address_space(1))) gvec2*)p;
+    T r;
+    __builtin_memcpy(&r, &v, 8);
+    return r;
+  } else if constexpr (sizeof(T) == 16 && alignof(T) >= 16) {
+    const gvec4 v = *(const __attribute__((address_space(1))) gvec4*)p;
+    T r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+  } else {
+    return *(const __attribute__((address_space(1))) T*)p;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // A raw packed sample held in registers until it is used (so that a prefetch
 // does not force the wait for the load at the point of issue).
 struct Raw {
   uint32_t x, y;
 };
 
+// Sample a of a packed row: load_raw reads a row anywhere (the calibration
+// solve reads rows staged in LDS), load_raw_global a row of the E-field
+// stream in global memory, with the address space stated.
 __device__ __forceinline__ Raw load_raw(const uint8_t* row, int a, int fmt) {
   Raw r;
   if (fmt == kCI4) {
@@ -26,6 +60,22 @@ __device__ __forceinline__ Raw load_raw(const uint8_t* row, int a, int fmt) {
     r.y = 0;
   } else {
     const uint2 v = reinterpret_cast<const uint2*>(row)[a];
+    r.x = v.x;
+    r.y = v.y;
+  }
+  return r;
+}
+
+__device__ __forceinline__ Raw load_raw_global(const uint8_t* row, int a, int fmt) {
+  Raw r;
+  if (fmt == kCI4) {
+    r.x = gload(row + a);
+    r.y = 0;
+  } else if (fmt == kCI8) {
+    r.x = gload(reinterpret_cast<const uint16_t*>(row) + a);
+    r.y = 0;
+  } else {
+    const uint2 v = gload(reinterpret_cast<const uint2*>(row) + a);
     r.x = v.x;
     r.y = v.y;
   }
@@ -45,6 +95,10 @@ __device__ __forceinline__ float2 unpack_raw(Raw r, int fmt) {
 
 __device__ __forceinline__ float2 load_sample(const uint8_t* row, int a, int fmt) {
   return unpack_raw(load_raw(row, a, fmt), fmt);
+}
+
+__device__ __forceinline__ float2 load_sample_global(const uint8_t* row, int a, int fmt) {
+  return unpack_raw(load_raw_global(row, a, fmt), fmt);
 }
 
 __device__ __forceinline__ void lds_add(float2* p, float2 v) {
@@ -88,7 +142,7 @@ constexpr int kLdsBytes = 163840 - 1024;                // LDS per workgroup on 
 
 // Copy the slot table (S x L entries) into LDS with the whole workgroup.
 __device__ __forceinline__ void load_slot_table(uint2* stab, const uint2* slots, int S, int L) {
-  for (int i = threadIdx.x; i < S * L; i += blockDim.x) stab[i] = slots[i];
+  for (int i = threadIdx.x; i < S * L; i += blockDim.x) stab[i] = gload(slots + i);
 }
 
 // Calibrate (E'_a = u_a E_a) into the frame's E' staging area.
@@ -142,8 +196,8 @@ __device__ __forceinline__ void fetch_frame(Raw (&raw)[APL], float2 (&uu)[APL], 
     constexpr int i = decltype(ic)::value;
     const int a = lam + N * i;
     if (active && a < Na) {
-      raw[i] = load_raw(row, a, fmt);
-      uu[i] = urow[a];
+      raw[i] = load_raw_global(row, a, fmt);
+      uu[i] = gload(urow + a);
     } else {
       raw[i] = Raw{0u, 0u};
       uu[i] = make_float2(0.f, 0.f);

@@ -76,8 +76,8 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
     for (int i = 0; i < MAXI; ++i) {
       const int an = tid + 256 * i;
       if (active && an < a.Na) {
-        raw[i] = load_raw(row, an, a.fmt);
-        uu[i] = urow[an];
+        raw[i] = load_raw_global(row, an, a.fmt);
+        uu[i] = gload(urow + an);
       } else {
         raw[i] = Raw{0u, 0u};
         uu[i] = make_float2(0.f, 0.f);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
     float2 sum = make_float2(0.f, 0.f);
 #pragma unroll 4
     for (int k = 0; k < a.n_slots; ++k) {
-      const uint2 e = stab[k * 64 + lane];
+      const uint2 e = BIG ? gload(a.slots + k * 64 + lane) : stab[k * 64 + lane];
       const uint32_t code = e.x;
       const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
       const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
   float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
   static_for<0, 64>([&](auto yc) {
     constexpr int y = decltype(yc)::value;
-    out[(R * y + cy) * N + R * lane + cx] = acc[y];
+    gstore(out + (R * y + cy) * N + R * lane + cx, acc[y]);
   });
   __syncthreads();
 }
@@ -226,7 +226,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
     static_for<0, APT>([&](auto ic) {
       const int an = gt + 256 * decltype(ic)::value;
-      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw_global(row, an, FMT).x : 0u;
     });
   };
   const int64_t iters = (te - tb + 1) / 2;
@@ -239,7 +239,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     float2 uu[APT];
     static_for<0, APT>([&](auto ic) {
       const int an = gt + 256 * decltype(ic)::value;
-      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+      uu[decltype(ic)::value] = gload(urow + (an < a.Na ? an : a.Na - 1));
     });
     static_for<0, APT>([&](auto ic) {
       const int an = gt + 256 * decltype(ic)::value;
@@ -283,7 +283,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
     static_for<0, NF>([&](auto yc) {
       constexpr int y = decltype(yc)::value;
-      out[(R * y + cy) * N + R * lam + cx] = acc[y] + red[(ci * NF + y) * NF + lam];
+      gstore(out + (R * y + cy) * N + R * lam + cx, acc[y] + red[(ci * NF + y) * NF + lam]);
     });
   }
   __syncthreads();

@@ -162,7 +162,7 @@ __device__ __forceinline__ void dft_item(const ImageArgs& a, int f, int s, uint8
 #pragma unroll
       for (int i = 0; i < APL; ++i) {
         const int an = lane + 64 * i;
-        if (an < a.Na) epr[an] = active ? cmul(load_sample(row, an, a.fmt), urow[an]) : make_float2(0.f, 0.f);
+        if (an < a.Na) epr[an] = active ? cmul(load_sample_global(row, an, a.fmt), gload(urow + an)) : make_float2(0.f, 0.f);
       }
       wave_lds_sync();
       grid_frame(gt, epr, stab, a.n_slots, 64, lane);
@@ -258,7 +258,7 @@ __device__ __forceinline__ void dft_item(const ImageArgs& a, int f, int s, uint8
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < D::FPI; ++q) sum += red[(((q * D::WPF + tyy) * D::T + tx) * 16 + v) * 64 + ln];
-    out[idx] = sum;
+    gstore(out + idx, sum);
   }
   __syncthreads();
 }
@@ -359,7 +359,7 @@ __device__ __forceinline__ void dft_cls_item(const ImageArgs& a, int f, int cp, 
       const int bpe = efmt_bytes(a.fmt);
       const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
       const float2* urow = a.u + ((t / a.t_cal) * a.F + f) * int64_t(a.Na);
-      for (int an = lane; an < a.Na; an += 64) epr[an] = cmul(load_sample(row, an, a.fmt), urow[an]);
+      for (int an = lane; an < a.Na; an += 64) epr[an] = cmul(load_sample_global(row, an, a.fmt), gload(urow + an));
       wave_lds_sync();
       // fold and phase the class: owned sub-cells, transposed layout
       float2 sum = make_float2(0.f, 0.f);
@@ -455,7 +455,7 @@ __device__ __forceinline__ void dft_cls_item(const ImageArgs& a, int f, int cp, 
     for (int v = 0; v < 16; ++v) {
       const int kx = tx * 32 + 8 * (v / 4) + 4 * h + v % 4;   // C row = kx of X^T
       const int ky = ty * 32 + li;                            // C column = ky
-      out[(R * ky + cy) * N + R * kx + cx] = acc[tx][v];
+      gstore(out + (R * ky + cy) * N + R * kx + cx, acc[tx][v]);
     }
   __syncthreads();
 }

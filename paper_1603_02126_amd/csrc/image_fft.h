@@ -70,7 +70,7 @@ __device__ __forceinline__ void image_item(const ImageArgs& a, int f, int s, uin
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];
-    out[idx] = sum;
+    gstore(out + idx, sum);
   }
   __syncthreads();
 }
@@ -140,7 +140,7 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw_global(row, an, FMT).x : 0u;
     });
   };
   fetch_raw(tb + wave);
@@ -156,7 +156,7 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     float2 uu[APL];
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+      uu[decltype(ic)::value] = gload(urow + (an < a.Na ? an : a.Na - 1));
     });
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
@@ -207,7 +207,7 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < 8; ++q) sum += red[q * N * N + idx];
-    out[idx] = sum;
+    gstore(out + idx, sum);
   }
   __syncthreads();
 }
@@ -252,7 +252,7 @@ __device__ __forceinline__ void snap_store(const ImageArgs& a, int f, int64_t j,
   float* out = a.snap + (j * a.F + f) * int64_t(N * N);
   static_for<0, N>([&](auto yc) {
     constexpr int y = decltype(yc)::value;
-    out[y * N + lam] = acc[y] * sc;
+    gstore(out + y * N + lam, acc[y] * sc);
     acc[y] = 0.f;
   });
 }
@@ -329,7 +329,7 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     const uint8_t* row = a.efield + (c.t() * a.F + f) * int64_t(a.Na) * bpe;
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      raw[decltype(ic)::value] = (ok && an < a.Na) ? load_raw(row, an, FMT).x : 0u;
+      raw[decltype(ic)::value] = (ok && an < a.Na) ? load_raw_global(row, an, FMT).x : 0u;
     });
   };
   // the waves are independent: each walks its own windows
@@ -342,7 +342,7 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     float2 uu[APL];
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;
-      uu[decltype(ic)::value] = urow[an < a.Na ? an : a.Na - 1];
+      uu[decltype(ic)::value] = gload(urow + (an < a.Na ? an : a.Na - 1));
     });
     static_for<0, APL>([&](auto ic) {
       const int an = lam + N * decltype(ic)::value;

@@ -28,14 +28,25 @@ __global__ void k_counter_reset(int* counter) {
 }
 
 // Each engine body is its own (non-inlined) function so that the register
-// allocation of one engine does not constrain the others.
+// allocation of one engine does not constrain the others.  Through the call
+// the arguments arrive as generic pointers: the engines state the address
+// space of their global accesses (gload / gstore), and each wrapper copies
+// the arguments once, so that the frame loop does not reload them with
+// generic (FLAT) loads, which would also count against the LDS wait counter.
 template <int N, int APL>
-__device__ __noinline__ void fft_call(const ImageArgs& a, int4 w, uint8_t* smem) { image_item<N, APL>(a, w.y, w.w, smem); }
+__device__ __noinline__ void fft_call(const ImageArgs& a, int4 w, uint8_t* smem) {
+  const ImageArgs la = a;
+  image_item<N, APL>(la, w.y, w.w, smem);
+}
 template <int N, int APL>
-__device__ __noinline__ void dft_call(const ImageArgs& a, int4 w, uint8_t* smem) { dft_item<N, APL>(a, w.y, w.w, smem); }
+__device__ __noinline__ void dft_call(const ImageArgs& a, int4 w, uint8_t* smem) {
+  const ImageArgs la = a;
+  dft_item<N, APL>(la, w.y, w.w, smem);
+}
 template <int R, bool BIG>
 __device__ __noinline__ void cls_call(const ImageArgs& a, int4 w, uint8_t* smem) {
-  image_cls_item<R, BIG>(a, w.y, w.z, w.w, smem);
+  const ImageArgs la = a;
+  image_cls_item<R, BIG>(la, w.y, w.z, w.w, smem);
 }
 
 // engine code: 100 * engine + N / 32 * 10 + param (APL or R)

@@ -952,10 +952,28 @@ static int solve_ps(const HostArray& h) {
   return RB % 16 == 0 ? 16 : RB % 4 == 0 ? 4 : 1;
 }
 
-// Work items {array, channel, class group, split}, most expensive first.
+// Arrays whose FFT engine has a two-waves-per-SIMD form (512-thread
+// workgroups) are imaged by their own launch in the batched form: the
+// persistent kernel runs 256-thread engine bodies.
+static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
+  const int code = engine_of(plan, ap), N = ap.h.nx;
+  ImageArgs ia{};
+  ia.Na = ap.h.na;
+  ia.fmt = ap.h.efmt;
+  ia.slots_h = ap.d_slots_h;
+  ia.n_slots_h0 = ap.n_slots_h0;
+  ia.n_slots_h1 = ap.n_slots_h1;
+  if (code / 100 == epic::kEngFft) return epic::pair_engine(ia, N);
+  if (code / 100 == epic::kEngCls) return epic::cls_pair_engine(ia, N);
+  return false;
+}
+
+// Work items {array, channel, class group, split}, most expensive first;
+// none for the arrays with their own launch.
 static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int64_t n_samples) {
   std::vector<int> key{int(n_samples & 0x7fffffff), int(n_samples >> 31)};
   for (size_t i = 0; i < lay.size(); ++i) key.push_back(lay[i].splits);
+  for (size_t i = 0; i < lay.size(); ++i) key.push_back(own_launch(plan, plan->arrays[i]) ? 1 : 0);
   if (key == plan->items_key && plan->d_items) return EPIC_OK;
   struct It {
     int4 w;
@@ -963,6 +981,7 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   };
   std::vector<It> items;
   for (size_t i = 0; i < lay.size(); ++i) {
+    if (own_launch(plan, plan->arrays[i])) continue;
     const HostArray& h = plan->arrays[i].h;
     const int N = h.nx, cg = N == 256 ? 4 : 1;
     const double per_frame = double(N) * N * std::log2(double(N) * N) / cg + 32.0 * h.na;
@@ -984,8 +1003,10 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
     plan->items_cap = w.size();
     plan->generation++;
   }
-  hipError_t e = hipMemcpy(plan->d_items, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "work list upload");
+  if (!w.empty()) {
+    hipError_t e = hipMemcpy(plan->d_items, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "work list upload");
+  }
   plan->n_items = int(w.size());
   plan->items_key = key;
   return EPIC_OK;
@@ -1105,8 +1126,23 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       if (e != hipSuccess) return hip_fail(e, "gain history conversion launch");
     }
   }
-  // imaging: one persistent launch over every array's work items
+  // imaging: the arrays with a two-waves-per-SIMD engine by their own
+  // launches, the others by one persistent launch over their work items
   {
+    Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
+    for (int i = 0; i < na_arr; ++i) {
+      ArrayPlan& ap = plan->arrays[i];
+      if (!own_launch(plan, ap)) continue;
+      const HostArray& h = ap.h;
+      ImageArgs ia{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt,
+                   reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal, ap.d_slots, ap.n_slots,
+                   lay[i].splits, reinterpret_cast<float*>(scr + lay[i].p_off), ap.d_slots_h, ap.n_slots_h0,
+                   ap.n_slots_h1};
+      hipError_t e = epic::launch_image(h.nx, ia, s);
+      if (e != hipSuccess) return hip_fail(e, "imaging launch");
+    }
+  }
+  if (plan->n_items > 0) {
     epic::BatchImageArgs b{};
     b.n_arrays = na_arr;
     for (int i = 0; i < na_arr; ++i) {

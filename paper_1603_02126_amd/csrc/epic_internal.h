@@ -175,6 +175,7 @@ int grid_pitch(int N);
 int cls_table_slots();
 bool image_supported(int N, int na, int n_slots);
 bool pair_engine(const ImageArgs& a, int N);   // the 64 x 64 two-waves-per-SIMD engine applies
+bool cls_pair_engine(const ImageArgs& a, int N);   // the 128 / 256 two-waves-per-SIMD class engine applies
 // Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64; its gridding
 // schedule has 64 lanes and transposed (G^T) cell offsets.
 bool dft_supported(int N, int na, int n_slots);

@@ -36,7 +36,7 @@ def _plan(wls, opts=None):
 
 
 def _small_uneven(n_chan=3, n_samples=60):
-    return synth.config_uneven(n_chan=n_chan, n_samples=n_samples, n_ants=(40, 100, 160, 600),
+    return synth.config_uneven(n_chan=n_chan, n_samples=n_samples, n_ants=(40, 200, 160, 600),
                                grids=(32, 64, 128, 256))
 
 

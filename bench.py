@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "f62fdcbc75c5cdbc33577a5c4811f67070577a3f66ca762dc4f2894117452b59",
-            "fetch_kib": 177013.3, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "f62fdcbc75c5cdbc33577a5c4811f67070577a3f66ca762dc4f2894117452b59",
-                      "fetch_kib": 239783.0, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "8fbc1dbdb5d658b79a3d3d7343b972865ed97437bbbfc79673877dd7201b658f",
+            "fetch_kib": 177000.7, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "8fbc1dbdb5d658b79a3d3d7343b972865ed97437bbbfc79673877dd7201b658f",
+                      "fetch_kib": 239359.3, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
 }
 
 

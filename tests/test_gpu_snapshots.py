@@ -99,3 +99,32 @@ def test_snapshot_errors(cuda):
     with pytest.raises(lib.EpicError):
         plan.run_snapshots(0, e, 20, 1, g, imgs)
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["band", "pixels"])
+def test_snapshots_follow_band_and_pixel_calibration(cuda, mode):
+    """Snapshots run the same calibration as epic_run, also with gains shared
+    over a band or taken from several pixels: identical gain history, and the
+    window images average to epic_run's image."""
+    from paper_1603_02126_amd import lib
+    from ._helpers import gpu_run, image_err
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, n_ant=200, n_chan=4, n_samples=250, t_cal=50)
+    packed = synth.make_efield(wl)
+
+    def plan():
+        p = lib.Plan([wl.array])
+        if mode == "band":
+            p.set_model(0, wl.model_lmS, wl.cal_lm, wl.gamma, wl.t_cal)
+            p.set_band(0, 0, 4, lib.BAND_MEAN)
+        else:
+            p.set_model_pixels(0, wl.model_lmS, wl.src_lmS[:3, :2], wl.gamma, wl.t_cal)
+        return p
+    p1 = plan()
+    run = gpu_run(wl, packed, cuda, plan=p1)
+    p1.close()
+    p2 = plan()
+    snaps, gh = _gpu_snap(wl, packed, 10, cuda, plan=p2)
+    p2.close()
+    np.testing.assert_array_equal(gh, run["hist"])
+    mean = snaps.astype(np.float64).mean(axis=0)
+    assert image_err(mean, run["image"]).max() <= 1e-5

@@ -145,6 +145,21 @@ __device__ __forceinline__ void load_slot_table(uint2* stab, const uint2* slots,
   for (int i = threadIdx.x; i < S * L; i += blockDim.x) stab[i] = gload(slots + i);
 }
 
+// Half-frame buffer of the two-waves-per-SIMD engines (kHalfPitch rows of
+// 32 cells): every lane takes the cells of its own row y = lane into
+// v[X0 .. X0 + 31] and clears them for the next half.
+template <int X0>
+__device__ __forceinline__ void take_half_row(float2 (&v)[64], float2* H, int lam) {
+  float2* row = H + lam * kHalfPitch;
+  static_for<0, 32>([&](auto xc) { v[X0 + decltype(xc)::value] = row[decltype(xc)::value]; });
+  static_for<0, 32>([&](auto xc) { row[decltype(xc)::value] = make_float2(0.f, 0.f); });
+}
+
+// Clears the lane's row of a half-frame buffer, pad column included.
+__device__ __forceinline__ void clear_half_row(float2* H, int lam) {
+  static_for<0, kHalfPitch>([&](auto xc) { H[lam * kHalfPitch + decltype(xc)::value] = make_float2(0.f, 0.f); });
+}
+
 // Calibrate (E'_a = u_a E_a) into the frame's E' staging area.
 template <int N, int APL>
 __device__ __forceinline__ void stage_frame(float2* epr, const Raw (&raw)[APL], const float2 (&uu)[APL], int lam,

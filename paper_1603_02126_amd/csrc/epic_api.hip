@@ -223,9 +223,10 @@ void model_tables(const HostArray& h, const epic_model_desc* m, ModelTables& t, 
 //   antenna | LDS cell offset << 12 | first-of-cell << 31,  weight bits.
 // Padding slots store zero into the pad column (offset = grid size).
 // Returns the slot count S; table is [S][L] (lane fastest), 2 words each.
-// Rows y0 <= y < y1 only (re-based so that row y0 is row 0) when y1 > y0.
+// half >= 0: the columns 32 half <= x < 32 half + 32 only, at offsets
+// y * kHalfPitch + x - 32 half of the half-frame buffer (pad: column 32).
 int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& table, bool transposed = false,
-                int y0 = 0, int y1 = 0) {
+                int half = -1) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
@@ -235,8 +236,8 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
     for (int k = 0; k < h.k2; ++k) {
       const size_t q = size_t(a) * h.k2 + k;
       if (w[q] == 0.0) continue;
-      if (y1 > y0 && (iy[q] < y0 || iy[q] >= y1)) continue;
-      cell[size_t(iy[q] - (y1 > y0 ? y0 : 0)) * h.nx + ix[q]].push_back({a, float(w[q])});
+      if (half >= 0 && ix[q] / 32 != half) continue;
+      cell[size_t(iy[q]) * h.nx + ix[q]].push_back({a, float(w[q])});
     }
   }
   std::vector<int> order;
@@ -254,13 +255,15 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
   }
   size_t S = 0;
   for (int l = 0; l < L; ++l) S = std::max(S, load[l]);
-  const uint32_t pad = uint32_t(h.nx) << 12;   // row 0, first pad column
+  const uint32_t pad = uint32_t(half >= 0 ? 32 : h.nx) << 12;   // row 0, first pad column
   table.assign(2 * S * L, 0u);
   for (int l = 0; l < L; ++l) {
     size_t s = 0;
     for (int c : lane_cells[l]) {
       const int cy = c / h.nx, cx = c % h.nx;
-      const uint32_t off = transposed ? uint32_t(cx * pitch + cy) : uint32_t(cy * pitch + cx);
+      const uint32_t off = half >= 0   ? uint32_t(cy * epic::kHalfPitch + cx - 32 * half)
+                           : transposed ? uint32_t(cx * pitch + cy)
+                                        : uint32_t(cy * pitch + cx);
       const auto& lst = cell[c];
       for (size_t i = 0; i < lst.size(); ++i, ++s) {
         uint32_t code = uint32_t(lst[i].first) | (off << 12);
@@ -284,8 +287,9 @@ int build_slots(const HostArray& h, int L, int pitch, std::vector<uint32_t>& tab
 // grouped by sub-cell q = j mod 64 and sub-cells are balanced over 64 lanes;
 // each slot keeps the full cell j = 64 p + q so that the kernel can apply the
 // class phase exp(+2 pi i j.c / N).
-// Sub-cell rows y0 <= qy < y1 only when y1 > y0 (the codes keep the full qy).
-int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int y0 = 0, int y1 = 0) {
+// half >= 0: the sub-cell columns 32 half <= qx < 32 half + 32 only (the
+// codes keep the full qx).
+int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int half = -1) {
   std::vector<int32_t> ix, iy;
   std::vector<double> w;
   grid_cells(h, ix, iy, w);
@@ -296,7 +300,7 @@ int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int y0 = 0
     for (int k = 0; k < h.k2; ++k) {
       const size_t q = size_t(a) * h.k2 + k;
       if (w[q] == 0.0) continue;
-      if (y1 > y0 && (iy[q] % 64 < y0 || iy[q] % 64 >= y1)) continue;
+      if (half >= 0 && (ix[q] % 64) / 32 != half) continue;
       sub[size_t(iy[q] % 64) * 64 + ix[q] % 64].push_back({a, ix[q], iy[q], float(w[q])});
     }
   }
@@ -673,8 +677,8 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       }
       if (!rc && ap.h.nx == 64) {
         std::vector<uint32_t> hi;
-        ap.n_slots_h0 = build_slots(ap.h, 64, epic::grid_pitch(64), tab, false, 0, 32);
-        ap.n_slots_h1 = build_slots(ap.h, 64, epic::grid_pitch(64), hi, false, 32, 64);
+        ap.n_slots_h0 = build_slots(ap.h, 64, epic::kHalfPitch, tab, false, 0);
+        ap.n_slots_h1 = build_slots(ap.h, 64, epic::kHalfPitch, hi, false, 1);
         tab.insert(tab.end(), hi.begin(), hi.end());
         rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }
@@ -684,8 +688,8 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       if (!rc) {
         std::vector<uint32_t> hi;
-        ap.n_slots_h0 = build_slots_cls(ap.h, tab, 0, 32);
-        ap.n_slots_h1 = build_slots_cls(ap.h, hi, 32, 64);
+        ap.n_slots_h0 = build_slots_cls(ap.h, tab, 0);
+        ap.n_slots_h1 = build_slots_cls(ap.h, hi, 1);
         tab.insert(tab.end(), hi.begin(), hi.end());
         rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }

@@ -26,10 +26,10 @@ struct ImageArgs {
   int n_slots;
   int splits;               // workgroups per channel
   float* partial;           // [splits][F][N*N]
-  // schedule of the half-frame gridding (64 lanes): rows 0..31, then rows
-  // 32..63; for 64 x 64 the cell offsets are re-based to row 0, for the
-  // residue-class engines the codes keep the sub-cell (the kernel re-bases);
-  // null when not built
+  // schedule of the half-frame gridding (64 lanes): columns 0..31, then
+  // columns 32..63; for 64 x 64 the cell offsets are re-based to column 0 of
+  // a kHalfPitch buffer, for the residue-class engines the codes keep the
+  // sub-cell (the kernel re-bases); null when not built
   const uint2* slots_h = nullptr;
   int n_slots_h0 = 0, n_slots_h1 = 0;
   // snapshot form: one image per window of t_acc samples, written to
@@ -165,6 +165,12 @@ hipError_t launch_image_batch(const BatchImageArgs& b, int n_workgroups, hipStre
 hipError_t launch_solve_batch(const BatchSolveArgs& b, int j, int ps, hipStream_t s);
 hipError_t launch_reduce_batch(const BatchReduceArgs& b, hipStream_t s);
 int cls_variant(int na, int n_slots);
+
+// Half-frame buffer of the two-waves-per-SIMD engines: the 64 rows of one
+// half of the columns (32 cells each) at a pitch of 33 complex values, so
+// that 64 lanes loading their own rows stay free of bank conflicts; column 32
+// is the pad that the schedule's padding slots write.
+constexpr int kHalfPitch = 33;
 
 // Launchers: return hipSuccess or the launch error.  N = grid size.
 // Gridding schedule geometry of the N <= 64 engine: lanes per frame and LDS

@@ -132,7 +132,7 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
 //
 // Eight waves: two frames (samples t, t + 1) x four classes of the class
 // group.  Each wave grids its class of its frame through half a 64 x 64 frame
-// (sub-cell rows 0..31, then 32..63, two schedules built on the host), runs
+// (sub-cell columns 0..31, then 32..63, two schedules built on the host), runs
 // the row FFTs, transposes in registers (xpose.h, the half frame as staging)
 // and runs the column FFTs, as the 64 x 64 paired engine does.  The E' of the
 // two frames is staged once per frame by its four waves; two workgroup
@@ -144,7 +144,7 @@ constexpr int kClsPairThreads = 512;
 template <int R>
 struct ClsPairSmem {
   static constexpr int N = 64 * R;
-  static constexpr int HALF = 32 * Geo<64>::PITCH;               // float2 per wave
+  static constexpr int HALF = 64 * kHalfPitch;                   // float2 per wave
   static constexpr int E_OFF = 8 * HALF * 8;                     // bytes
   static constexpr int TW_OFF = E_OFF + 2 * kClsMaxAnt * 8;
   static constexpr int T_OFF = TW_OFF + N * 8;
@@ -154,12 +154,12 @@ struct ClsPairSmem {
   static_assert(4 * 64 * 64 * 4 <= E_OFF, "the class reduction reuses the half frames");
 };
 
-// Grid sub-cell rows [32 hf, 32 hf + 32) of class (cx, cy) into the half
-// frame H (row qy - 32 hf), slots in batches of B.
+// Grid sub-cell columns [32 hf, 32 hf + 32) of class (cx, cy) into the half
+// frame H (column qx - 32 hf), slots in batches of B.
 template <int R, int B>
 __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, const float2* tw, const uint2* stab,
                                               int S, int hf, int cx, int cy, int lam) {
-  constexpr int N = 64 * R, P = Geo<64>::PITCH;
+  constexpr int N = 64 * R;
   float2 sum = make_float2(0.f, 0.f);
   for (int s0 = 0; s0 < S; s0 += B) {
     uint2 e[B];
@@ -185,7 +185,7 @@ __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, cons
       sum.x = first ? c.x : sum.x + c.x;
       sum.y = first ? c.y : sum.y + c.y;
       const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
-      const int off = (code >> 30) & 1 ? (qy - 32 * hf) * P + qx : 64;
+      const int off = (code >> 30) & 1 ? qy * kHalfPitch + qx - 32 * hf : 32;
       if (s0 + k < S) H[off] = sum;
     });
   }
@@ -194,7 +194,7 @@ __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, cons
 template <int R, int FMT>
 __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
-  constexpr int N = 64 * R, P = Geo<64>::PITCH, NF = 64;
+  constexpr int N = 64 * R, NF = 64;
   using L = ClsPairSmem<R>;
   float2* lds = reinterpret_cast<float2*>(smem);
   const int tid = threadIdx.x, lam = tid & 63, wave = tid >> 6;
@@ -216,7 +216,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     sincospi(2.0 * double(k) / double(N), &sn, &cs);
     tw[k] = make_float2(float(cs), float(sn));
   }
-  if (lam < 32) static_for<0, NF>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  clear_half_row(H, lam);
 
   float acc[NF];
   static_for<0, NF>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
@@ -250,17 +250,11 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     __syncthreads();
     grid_cls_half<R, 4>(H, epr, tw, stab, S0, 0, cx, cy, lam);
     wave_lds_sync();
-    if (lam < 32) {
-      static_for<0, NF>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
-      static_for<0, NF>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<0>(v, H, lam);
     wave_lds_sync();
     grid_cls_half<R, 4>(H, epr, tw, stab + S0 * 64, S1, 1, cx, cy, lam);
     wave_lds_sync();
-    if (lam >= 32) {
-      static_for<0, NF>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
-      static_for<0, NF>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<32>(v, H, lam);
     __syncthreads();   // every wave is done with this pair's E'
     __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);

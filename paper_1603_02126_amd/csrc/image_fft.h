@@ -87,10 +87,9 @@ namespace epic {
 // computing at the same time.  The one-wave engine above needs a 33 KB frame
 // buffer per wave, which leaves room for one wave per SIMD; here each of the
 // eight waves of a workgroup (two per SIMD) images its own frames with 19 KB:
-//   * gridding goes through half a frame (32 rows): the rows 0..31 are
-//     gridded and loaded by lanes 0..31, then the rows 32..63 by lanes
-//     32..63 (two schedules, built on the host), each lane zeroing the row it
-//     loaded;
+//   * gridding goes through half a frame (32 columns): the columns 0..31 are
+//     gridded, then every lane loads the half of its row y = lane and clears
+//     it; then the columns 32..63 (two schedules, built on the host);
 //   * after the row FFTs the frame is transposed in registers (xpose.h),
 //     with the same half buffer as staging for the low index bits;
 //   * column FFTs and |X|^2 accumulation as in the one-wave engine.
@@ -101,7 +100,7 @@ constexpr int kPairThreads = 512;
 
 template <int APL>
 struct PairSmem {
-  static constexpr int HALF = 32 * Geo<64>::PITCH;        // float2: half frame
+  static constexpr int HALF = 64 * kHalfPitch;            // float2: half frame
   static constexpr int WAVE = HALF + APL * 64;            // float2 per wave: half frame + E' staging
   static constexpr int T_OFF = 8 * WAVE * 8;              // bytes: slot table
   static constexpr int TAB_SLOTS = (kLdsBytes - T_OFF) / (64 * 8);
@@ -113,7 +112,7 @@ struct PairSmem {
 template <int APL, int FMT>
 __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
-  constexpr int N = 64, P = Geo<64>::PITCH, INFLIGHT = 8;
+  constexpr int N = 64, INFLIGHT = 8;
   using L = PairSmem<APL>;
   float2* lds = reinterpret_cast<float2*>(smem);
   const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -124,7 +123,7 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
   const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
 
   load_slot_table(stab, a.slots_h, S0 + S1, N);
-  if (lam < 32) static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  clear_half_row(H, lam);
   __syncthreads();
 
   float acc[N];
@@ -165,21 +164,15 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
                                       : make_float2(0.f, 0.f);
     });
     wave_lds_sync();
-    // rows 0..31: grid, lanes 0..31 load their row and zero it
+    // columns 0..31: grid, every lane loads its row's half and clears it
     grid_frame<8>(H, epr, stab, S0, N, lam);
     wave_lds_sync();
-    if (lam < 32) {
-      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
-      static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<0>(v, H, lam);
     wave_lds_sync();
-    // rows 32..63
+    // columns 32..63
     grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
     wave_lds_sync();
-    if (lam >= 32) {
-      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
-      static_for<0, N>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<32>(v, H, lam);
     wave_lds_sync();
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along x: lane = row y
@@ -304,7 +297,7 @@ __device__ __forceinline__ void image_item_snap(const ImageArgs& a, int f, int s
 template <int APL, int FMT>
 __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
-  constexpr int N = 64, P = Geo<64>::PITCH, INFLIGHT = 8;
+  constexpr int N = 64, INFLIGHT = 8;
   using L = PairSmem<APL>;
   float2* lds = reinterpret_cast<float2*>(smem);
   const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -316,7 +309,7 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
   const int64_t wb = W * s / a.splits, we = W * (s + 1) / a.splits;
 
   load_slot_table(stab, a.slots_h, S0 + S1, N);
-  if (lam < 32) static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
+  clear_half_row(H, lam);
   __syncthreads();
 
   float acc[N];
@@ -351,17 +344,11 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     wave_lds_sync();
     grid_frame<8>(H, epr, stab, S0, N, lam);
     wave_lds_sync();
-    if (lam < 32) {
-      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[lam * P + decltype(xc)::value]; });
-      static_for<0, N>([&](auto xc) { H[lam * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<0>(v, H, lam);
     wave_lds_sync();
     grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
     wave_lds_sync();
-    if (lam >= 32) {
-      static_for<0, N>([&](auto xc) { v[decltype(xc)::value] = H[(lam - 32) * P + decltype(xc)::value]; });
-      static_for<0, N>([&](auto xc) { H[(lam - 32) * P + decltype(xc)::value] = make_float2(0.f, 0.f); });
-    }
+    take_half_row<32>(v, H, lam);
     wave_lds_sync();
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);

@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "8fbc1dbdb5d658b79a3d3d7343b972865ed97437bbbfc79673877dd7201b658f",
-            "fetch_kib": 177000.7, "fetch_scale": 2.000, "write_kib": 45056.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "8fbc1dbdb5d658b79a3d3d7343b972865ed97437bbbfc79673877dd7201b658f",
-                      "fetch_kib": 239359.3, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800",
+            "fetch_kib": 175015.9, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800",
+                      "fetch_kib": 237309.2, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
 }
 
 

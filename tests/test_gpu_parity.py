@@ -181,6 +181,36 @@ def test_run_flagged_antennas(cuda):
     np.testing.assert_array_equal(got["gains"][:, flags == 1], wl.g0[:, flags == 1])
 
 
+@pytest.mark.parametrize("layout", ["one_half", "edges"])
+def test_paired_engine_half_frame_edges(cuda, layout):
+    """The 64 x 64 two-waves-per-SIMD engine grids a frame in two halves of 32
+    columns.  'one_half': every cell lies in columns 0..31, so the second
+    half's schedule is empty.  'edges': 2 x 2 kernels that straddle columns
+    31/32, or wrap around the last column and row (cell indices mod N)."""
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, n_ant=160, n_chan=2, n_samples=120, t_cal=40)
+    a = wl.array
+    rng = np.random.default_rng(5)
+    if layout == "one_half":
+        p = np.column_stack([rng.uniform(1.0, 30.0, 160), rng.uniform(1.0, 62.0, 160)])
+    else:
+        px = np.concatenate([rng.uniform(31.0, 32.0, 60), rng.uniform(63.0, 64.0, 50), rng.uniform(5.0, 58.0, 50)])
+        py = np.concatenate([rng.uniform(3.0, 60.0, 60), rng.uniform(3.0, 60.0, 50), rng.uniform(63.0, 64.0, 50)])
+        p = np.column_stack([px, py])
+    xy = np.column_stack([a.x0 + p[:, 0] * a.dx, a.y0 + p[:, 1] * a.dy])
+    wl = wl.replace(array=synth.dataclasses.replace(a, ant_xy=xy))
+    cells = O.grid_cells(xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    ix = np.asarray(cells.ix)[np.asarray(cells.w) > 0]
+    if layout == "one_half":
+        assert ix.max() < 32
+    else:
+        assert {31, 32, 63, 0} <= set(ix.tolist())
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
 @pytest.mark.parametrize("splits", [1, 3, 64])
 def test_run_split_counts_agree(cuda, splits):
     """Any time split of the imaging launch gives the same answer."""

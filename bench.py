@@ -58,6 +58,23 @@ TRAFFIC_MEASURED = {
 }
 
 
+# Issue-slot and LDS use of the LWA imaging kernel from rocprofv3 --pmc SQ
+# counters (same validity rule as the traffic figures): the fraction of its
+# SIMDs' FP32 issue rate the VALU instructions use (SQ_ACTIVE_INST_VALU per
+# wave, two waves per SIMD, four cycles per instruction and wave) and the
+# fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
+SQ_MEASURED = {
+    "lwa": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800", "valu_issue_frac": 0.49, "lds_busy_frac": 0.51},
+}
+
+
+def measured_sq(workload_name):
+    m = SQ_MEASURED.get(workload_name)
+    if m is None or m["sources_sha256"] != imaging_sources_digest():
+        return None
+    return {k: v for k, v in m.items() if k != "sources_sha256"}
+
+
 def imaging_sources_digest():
     import hashlib
     h = hashlib.sha256()
@@ -415,7 +432,8 @@ def bench_single(args, dev):
                      "kernel": engine, "avg_launch_ms": avg_img_ms,
                      "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
                      "hbm_bytes_per_frame": bytes_launch / frames,
-                     "hbm_frac": bytes_launch / (avg_img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+                     "hbm_frac": bytes_launch / (avg_img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "sq_counters": measured_sq(args.workload) if not args.splits else None},
         "kernels": kernels,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

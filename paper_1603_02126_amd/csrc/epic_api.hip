@@ -485,8 +485,9 @@ int check_grid_supported(const ArrayPlan& ap, bool small = false) {
                 "support 128 and 256", h.nx);
   if (!epic::image_supported(h.nx, h.na, ap.n_slots))
     return fail(EPIC_ERR_UNSUPPORTED,
-                "grid %d with %d antennas is not supported (N in {16,32,64}: Na <= 8N; N in {128,256}: Na <= 512; "
-                "gridding schedule of %d slots per lane too long)", h.nx, h.na, ap.n_slots);
+                "grid %d with %d antennas is not supported (N in {16,32,64}: Na <= 8N and a gridding schedule "
+                "that fits the LDS slot table, here %d slots per lane; N in {128,256}: Na <= 2048)",
+                h.nx, h.na, ap.n_slots);
   return EPIC_OK;
 }
 

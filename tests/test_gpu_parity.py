@@ -167,6 +167,29 @@ def test_run_small(cuda, n, efmt, kernel, na, n_samples, t_cal):
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
 
 
+@pytest.mark.parametrize("n,efmt,kernel,na,n_samples,t_cal", [
+    (16, synth.FMT_CI8, 2, 128, 40, 20),     # 8 N antennas: the FFT engines' limit
+    (64, synth.FMT_CI4, 1, 512, 30, 16),     # 8 N at 64 x 64 (the 2 x 2 kernel's schedule would not fit)
+    (256, synth.FMT_CI8, 2, 2048, 12, 6),    # the residue-class engines' limit
+])
+def test_run_maximum_antennas(cuda, n, efmt, kernel, na, n_samples, t_cal):
+    wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_chan=2, n_samples=n_samples, t_cal=t_cal)
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
+def test_dense_64_grid_with_2x2_kernel_is_an_error(cuda):
+    """512 antennas with the 2 x 2 kernel give a 64 x 64 gridding schedule
+    longer than the LDS slot table: a clean EPIC_ERR_UNSUPPORTED."""
+    lib = _lib()
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, kernel=2, n_ant=512, n_chan=2, n_samples=30, t_cal=16)
+    with pytest.raises(lib.EpicError, match="slots per lane"):
+        gpu_run(wl, synth.make_efield(wl), cuda)
+
+
 def test_run_flagged_antennas(cuda):
     wl = synth.config_small(n_samples=150, t_cal=50)
     flags = np.zeros(wl.array.n_ant, np.uint8)

@@ -1302,9 +1302,7 @@ int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int6
   if (t_acc < 1) return fail(EPIC_ERR_ARG, "t_acc must be >= 1");
   if (!efield || !gains || !images) return fail(EPIC_ERR_ARG, "efield, gains and images must not be NULL");
   const int64_t n_win = (n_samples + t_acc - 1) / t_acc;
-  // every split holds at least one window; the splits fill the chip as in epic_run
-  int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
-  splits = int(std::min<int64_t>(splits, std::max<int64_t>(1, n_win / slots_for(ap.h.nx))));
+  const int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
   RunLayout lay{};
   size_t need = 0;
   bool any_band = false;
@@ -1326,6 +1324,10 @@ int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int6
   ia.t_acc = t_acc;
   ia.snap = images;
   ia.snap_scale = 1.0 / (double(h.na_eff) * double(h.na_eff));
+  // every split holds at least one window per frame slot (per workgroup when
+  // its waves share long windows); the splits fill the chip as in epic_run
+  const bool group = t_acc >= epic::kSnapGroupWindow && epic::pair_engine(ia, h.nx);
+  ia.splits = int(std::min<int64_t>(splits, std::max<int64_t>(1, n_win / (group ? 1 : slots_for(h.nx)))));
   Timed tm(plan, EPIC_TIMER_IMAGE, s, true);
   hipError_t e = epic::launch_image_snap(h.nx, ia, s);
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "snapshot imaging launch");

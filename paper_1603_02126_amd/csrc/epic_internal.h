@@ -166,6 +166,10 @@ hipError_t launch_solve_batch(const BatchSolveArgs& b, int j, int ps, hipStream_
 hipError_t launch_reduce_batch(const BatchReduceArgs& b, hipStream_t s);
 int cls_variant(int na, int n_slots);
 
+// Snapshot windows of at least this many samples are imaged by all eight
+// waves of a paired-engine workgroup together; shorter ones by one wave each.
+constexpr int64_t kSnapGroupWindow = 64;
+
 // Half-frame buffer of the two-waves-per-SIMD engines: the 64 rows of one
 // half of the columns (32 cells each) at a pitch of 33 complex values, so
 // that 64 lanes loading their own rows stay free of bank conflicts; column 32

@@ -109,25 +109,15 @@ struct PairSmem {
   static_assert(8 * 64 * 64 * 4 <= T_OFF, "the accumulator reduction reuses the wave areas");
 };
 
+// The eight waves' share of the frames [tb, te) of channel f: wave w images
+// tb + w, tb + w + 8, ... and adds |X|^2 into acc (lane = kx, acc[y] = ky).
+// The wave's half frame is zero on entry and on exit.
 template <int APL, int FMT>
-__device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s, uint8_t* smem) {
+__device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t tb, int64_t te, float (&acc)[64],
+                                            float2* H, float2* epr, const uint2* stab, int lam, int wave) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
   constexpr int N = 64, INFLIGHT = 8;
-  using L = PairSmem<APL>;
-  float2* lds = reinterpret_cast<float2*>(smem);
-  const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float2* H = lds + wave * L::WAVE;
-  float2* epr = H + L::HALF;
-  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
   const int S0 = a.n_slots_h0, S1 = a.n_slots_h1;
-  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
-
-  load_slot_table(stab, a.slots_h, S0 + S1, N);
-  clear_half_row(H, lam);
-  __syncthreads();
-
-  float acc[N];
-  static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
   float2 v[N];
   uint32_t raw[APL];   // integer formats only: one packed sample per register
   const int64_t iters = (te - tb + INFLIGHT - 1) / INFLIGHT;
@@ -186,22 +176,48 @@ __device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s
     fetch_raw(t + INFLIGHT);
     static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
   }
+}
 
-  // workgroup reduction of the eight accumulators
+// Workgroup sum of the eight waves' accumulators, times `scale`, into
+// out[64 * 64] (row-major ky, kx); the accumulators are zeroed.  The sums go
+// through the wave areas, whose half frames are cleared again afterwards.
+template <int APL>
+__device__ __forceinline__ void pair_reduce(float (&acc)[64], float* out, float scale, uint8_t* smem, int lam,
+                                            int wave) {
+  constexpr int N = 64;
   __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);
+  float* red = reinterpret_cast<float*>(smem);
   static_for<0, N>([&](auto yc) {
     constexpr int y = decltype(yc)::value;
     red[(wave * N + y) * N + lam] = acc[y];
+    acc[y] = 0.f;
   });
   __syncthreads();
-  float* out = a.partial + (int64_t(s) * a.F + f) * (N * N);
   for (int idx = threadIdx.x; idx < N * N; idx += kPairThreads) {
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < 8; ++q) sum += red[q * N * N + idx];
-    gstore(out + idx, sum);
+    gstore(out + idx, sum * scale);
   }
+  __syncthreads();
+  clear_half_row(reinterpret_cast<float2*>(smem) + wave * PairSmem<APL>::WAVE, lam);
+}
+
+template <int APL, int FMT>
+__device__ __forceinline__ void image_item_pair(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  using L = PairSmem<APL>;
+  const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float2* H = reinterpret_cast<float2*>(smem) + wave * L::WAVE;
+  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
+  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
+
+  load_slot_table(stab, a.slots_h, a.n_slots_h0 + a.n_slots_h1, 64);
+  clear_half_row(H, lam);
+  __syncthreads();
+  float acc[64];
+  static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  pair_frames<APL, FMT>(a, f, tb, te, acc, H, H + L::HALF, stab, lam, wave);
+  pair_reduce<APL>(acc, a.partial + (int64_t(s) * a.F + f) * (64 * 64), 1.f, smem, lam, wave);
   __syncthreads();
 }
 
@@ -217,7 +233,9 @@ namespace epic {
 // a wave of the paired engine) takes whole windows in turn, accumulates their
 // frames in registers and stores the window's image itself: no reduction
 // between slots, no atomics, and every store writes a row of N contiguous
-// pixels.
+// pixels.  Long windows would leave most of the paired engine's waves idle
+// (a channel split has few of them); there its eight waves share each
+// window and sum it through LDS.
 // ---------------------------------------------------------------------------
 
 // Walks one slot's frames: windows j = j0, j0 + stride, ... below j_end
@@ -242,10 +260,13 @@ template <int N>
 __device__ __forceinline__ void snap_store(const ImageArgs& a, int f, int64_t j, float (&acc)[N], int lam) {
   const int64_t len = min(a.t_acc, a.n_t - j * a.t_acc);
   const float sc = float(a.snap_scale / double(len));
-  float* out = a.snap + (j * a.F + f) * int64_t(N * N);
+  // the images are not read again by this kernel: streaming (nontemporal)
+  // stores keep them from displacing the E-field stream and u in the caches
+  __attribute__((address_space(1))) float* out =
+      (__attribute__((address_space(1))) float*)(a.snap + (j * a.F + f) * int64_t(N * N));
   static_for<0, N>([&](auto yc) {
     constexpr int y = decltype(yc)::value;
-    gstore(out + y * N + lam, acc[y] * sc);
+    __builtin_nontemporal_store(acc[y] * sc, out + y * N + lam);
     acc[y] = 0.f;
   });
 }
@@ -363,6 +384,32 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
     if (cur.last()) snap_store<N>(a, f, cur.j, acc, lam);
     cur = nxt;
+  }
+  __syncthreads();
+}
+
+// Long windows (t_acc >= kSnapGroupWindow) on the paired engine: the eight
+// waves share each window's frames, as in the averaging engine, and the
+// workgroup sums them into the window's image.
+template <int APL, int FMT>
+__device__ __forceinline__ void image_item_pair_snap_group(const ImageArgs& a, int f, int s, uint8_t* smem) {
+  using L = PairSmem<APL>;
+  const int lam = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float2* H = reinterpret_cast<float2*>(smem) + wave * L::WAVE;
+  uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
+  const int64_t W = (a.n_t + a.t_acc - 1) / a.t_acc;
+  const int64_t wb = W * s / a.splits, we = W * (s + 1) / a.splits;
+
+  load_slot_table(stab, a.slots_h, a.n_slots_h0 + a.n_slots_h1, 64);
+  clear_half_row(H, lam);
+  __syncthreads();
+  float acc[64];
+  static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  for (int64_t j = wb; j < we; ++j) {
+    const int64_t t0 = j * a.t_acc, t1 = min(t0 + a.t_acc, a.n_t);
+    pair_frames<APL, FMT>(a, f, t0, t1, acc, H, H + L::HALF, stab, lam, wave);
+    pair_reduce<APL>(acc, a.snap + (j * a.F + f) * int64_t(64 * 64), float(a.snap_scale / double(t1 - t0)), smem,
+                     lam, wave);
   }
   __syncthreads();
 }

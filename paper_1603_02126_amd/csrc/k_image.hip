@@ -59,6 +59,13 @@ __global__ __launch_bounds__(kPairThreads) void k_image_pair_snap(ImageArgs a) {
   image_item_pair_snap<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
+template <int APL, int FMT>
+__global__ __launch_bounds__(kPairThreads) void k_image_pair_snap_group(ImageArgs a) {
+  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
+  image_item_pair_snap_group<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_image_cls(ImageArgs a) {
   __shared__ __align__(16) uint8_t smem[ClsSmem<R, false>::BYTES];
@@ -264,8 +271,14 @@ struct LaunchImageSnap {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
     if constexpr (N == 64 && APL == 4) {
       if (pair_engine(a, N)) {
-        if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair_snap<APL, kCI4>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_image_pair_snap<APL, kCI8>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
+        const dim3 grid(a.F * a.splits), block(kPairThreads);
+        if (a.t_acc >= kSnapGroupWindow) {
+          if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair_snap_group<APL, kCI4>), grid, block, 0, s, a);
+          else hipLaunchKernelGGL((k_image_pair_snap_group<APL, kCI8>), grid, block, 0, s, a);
+        } else {
+          if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair_snap<APL, kCI4>), grid, block, 0, s, a);
+          else hipLaunchKernelGGL((k_image_pair_snap<APL, kCI8>), grid, block, 0, s, a);
+        }
         return hipGetLastError();
       }
     }

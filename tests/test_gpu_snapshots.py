@@ -53,6 +53,9 @@ def _window_err(got, ref):
     (16, synth.FMT_CF32, 1, 30, 2, 64, 7, 64),      # one window
     (16, synth.FMT_CF32, 1, 30, 2, 64, 7, 100),     # a window longer than the run
     (64, synth.FMT_CF32, 2, 100, 2, 90, 30, 4),     # one-wave engine at 64 x 64
+    (64, synth.FMT_CI4, 2, 256, 2, 410, 100, 64),   # paired engine, the eight waves share each window
+    (64, synth.FMT_CI8, 2, 140, 3, 300, 50, 97),    # ... with a ragged last window
+    (64, synth.FMT_CI4, 2, 200, 1, 150, 50, 200),   # ... one window longer than the run
 ])
 def test_snapshots_match_oracle(cuda, n, efmt, kernel, na, n_chan, n_samples, t_cal, t_acc):
     wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_chan=n_chan, n_samples=n_samples,
@@ -66,13 +69,15 @@ def test_snapshots_match_oracle(cuda, n, efmt, kernel, na, n_chan, n_samples, t_
     assert _window_err(got, ref) <= IMAGE_RTOL
 
 
-def test_snapshots_average_to_the_run_image(cuda):
-    """The length-weighted mean of the windows equals epic_run's image."""
+@pytest.mark.parametrize("t_acc", [25, 80])
+def test_snapshots_average_to_the_run_image(cuda, t_acc):
+    """The length-weighted mean of the windows equals epic_run's image (one
+    wave per window, and the eight waves sharing each window)."""
     from ._helpers import gpu_run, image_err
     wl = synth.config_small(n=64, efmt=synth.FMT_CI4, n_ant=220, n_chan=3, n_samples=403, t_cal=100)
     packed = synth.make_efield(wl)
-    got, _ = _gpu_snap(wl, packed, 25, cuda)
-    lens = np.array([25] * 16 + [3], float)
+    got, _ = _gpu_snap(wl, packed, t_acc, cuda)
+    lens = np.array([t_acc] * (403 // t_acc) + [403 % t_acc], float)
     mean = np.tensordot(lens, got.astype(np.float64), 1) / 403
     run = gpu_run(wl, packed, cuda)
     assert image_err(mean, run["image"]).max() <= 1e-5

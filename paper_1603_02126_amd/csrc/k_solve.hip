@@ -12,6 +12,14 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(SolveArgs a) {
   solve_channel<J, PS>(a, blockIdx.x, smem);
 }
 
+// One wave per channel: small arrays with short intervals.
+__global__ __launch_bounds__(64) void k_solve_wave(SolveArgs a) {
+  __shared__ float2 ring[kSolveWaveRows * 64];
+  if (a.fmt == kCI4) solve_channel_wave<kCI4>(a, blockIdx.x, ring);
+  else if (a.fmt == kCI8) solve_channel_wave<kCI8>(a, blockIdx.x, ring);
+  else solve_channel_wave<kCF32>(a, blockIdx.x, ring);
+}
+
 // ---------------------------------------------------------------------------
 // Stage-wise EPICal accumulate / finalize: one workgroup per channel.
 // ---------------------------------------------------------------------------
@@ -80,6 +88,10 @@ static hipError_t launch_solve_j(const SolveArgs& a, hipStream_t s) {
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   if (!solve_supported(a.Na, a.fmt, a.n_pix)) return hipErrorInvalidValue;
+  if (a.Na <= kSolveWaveMaxAnt && a.n_pix == 1 && a.t_cal <= kSolveWaveMaxTcal) {
+    hipLaunchKernelGGL(k_solve_wave, dim3(a.F), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
   if (a.Na <= kSolveThreads) return launch_solve_j<1>(a, s);
   return launch_solve_j<2>(a, s);
 }

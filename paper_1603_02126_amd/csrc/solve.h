@@ -283,6 +283,98 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
 }
 
 // ---------------------------------------------------------------------------
+// EPICal solve of one channel by a single wave, for small arrays with short
+// calibration intervals (Na <= 64, t_cal <= kSolveWaveMaxTcal).  There the
+// recursion is a chain of tiny dependent steps and its latency sets the time:
+// lane a owns antenna a, the tap of a sample is a wave-wide DPP sum (no
+// workgroup barriers), and the samples stream through a 64-row LDS block that
+// is requested one block ahead, so no step waits on memory.
+// ---------------------------------------------------------------------------
+constexpr int kSolveWaveMaxAnt = 64;
+constexpr int kSolveWaveMaxTcal = 8;
+constexpr int kSolveWaveRows = 64;
+
+// Sum of x over the 64 lanes, returned to every lane.
+__device__ __forceinline__ double wave_sum64(double x) {
+  x = row16_sum_lane15(x);                       // lane 16 r + 15: sum of row r
+  x += dpp_f64<0x142, 0xa>(x);                   // row_bcast:15 -> lanes 31, 63: rows 0+1, 2+3
+  x += dpp_f64<0x143, 0xc>(x);                   // row_bcast:31 -> lane 63: all four rows
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(b), 63), hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __longlong_as_double(static_cast<long long>(static_cast<unsigned>(lo)) | (static_cast<long long>(hi) << 32));
+}
+
+template <int FMT>
+__device__ __forceinline__ void solve_channel_wave(const SolveArgs& a, int f, float2* ring) {
+  const int lane = threadIdx.x & 63;
+  const bool own = lane < a.Na;
+  constexpr int bpe = FMT == kCF32 ? 8 : FMT == kCI8 ? 2 : 1;
+  const int64_t rowstride = int64_t(a.F) * a.Na * bpe;
+  const uint8_t* ebase = a.efield + int64_t(f) * a.Na * bpe;
+  const int64_t ia = int64_t(f) * a.Na + (own ? lane : 0);
+  double2 g = make_double2(0.0, 0.0), A = g, D = g;
+  uint8_t hold = 0;
+  uint32_t st = 0u;
+  if (own) {
+    g = a.gains[ia];
+    A = a.A[ia];
+    D = a.D[ia];
+    hold = a.hold[ia];
+    a.g_hist[ia] = g;
+  }
+  // samples of rows [64 b, 64 b + 64) for this lane's antenna, one block ahead
+  float2 pre[kSolveWaveRows];
+  auto request = [&](int64_t b) {
+    static_for<0, kSolveWaveRows>([&](auto kc) {
+      const int64_t t = b * kSolveWaveRows + decltype(kc)::value;
+      pre[decltype(kc)::value] = (own && t < a.n_t) ? load_sample_global(ebase + t * rowstride, lane, FMT)
+                                                    : make_float2(0.f, 0.f);
+    });
+  };
+  request(0);
+  double2 c = make_double2(0.0, 0.0);
+  auto coefficient = [&]() {
+    double2 u = zrecip(g);
+    if (!own || (hold & kHoldFlagged)) u = make_double2(0.0, 0.0);
+    const double2 cc = zmul(A, u);
+    c = make_double2(cc.x / a.na_eff, cc.y / a.na_eff);
+  };
+  coefficient();
+  double kx = 0.0, ky = 0.0, q = 0.0;
+  int n = 0;
+  int64_t t_end = min(a.t_cal, a.n_t);
+  for (int64_t t = 0; t < a.n_t; ++t) {
+    if ((t & (kSolveWaveRows - 1)) == 0) {
+      // entering block t / 64: its samples arrived during the previous block
+      static_for<0, kSolveWaveRows>([&](auto kc) { ring[decltype(kc)::value * 64 + lane] = pre[decltype(kc)::value]; });
+      wave_lds_sync();
+      request(t / kSolveWaveRows + 1);
+    }
+    const float2 e = ring[(t & (kSolveWaveRows - 1)) * 64 + lane];
+    const double ex = e.x, ey = e.y;
+    // tap P(t) = sum_a c_a E_a(t), then K_a += E_a conj(P), Q_a += |E_a|^2
+    const double px = wave_sum64(fma(c.x, ex, -c.y * ey));
+    const double py = wave_sum64(fma(c.x, ey, c.y * ex));
+    kx = fma(ex, px, fma(ey, py, kx));
+    ky = fma(ey, px, fma(-ex, py, ky));
+    q = fma(ex, ex, fma(ey, ey, q));
+    if (t + 1 == t_end) {
+      const double inv_n = 1.0 / double(t_end - int64_t(n) * a.t_cal);
+      g = epical_step(make_double2(kx * inv_n, ky * inv_n), q * inv_n, A, D, g, hold, a.na_eff, a.gamma, &st);
+      if (own) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + lane] = g;
+      kx = ky = q = 0.0;
+      ++n;
+      t_end = min(t_end + a.t_cal, a.n_t);
+      coefficient();
+    }
+  }
+  if (own) {
+    a.gains[ia] = g;
+    if (a.status) a.status[ia] |= st;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // EPICal from several tapped pixels (the multiple-pixel extension of Sec. 6):
 // per interval the taps P_p(t) = sum_a c_pa E_a(t) of every pixel, the
 // correlations K_ap = <E_a P_p*>, and the least-squares update over the

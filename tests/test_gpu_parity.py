@@ -190,6 +190,30 @@ def test_dense_64_grid_with_2x2_kernel_is_an_error(cuda):
         gpu_run(wl, synth.make_efield(wl), cuda)
 
 
+@pytest.mark.parametrize("n,efmt,kernel,na,n_samples,t_cal,flagged", [
+    (32, synth.FMT_CI4, 2, 64, 203, 1, ()),         # all 64 lanes own an antenna; four 64-row blocks, the last partial
+    (16, synth.FMT_CI8, 1, 17, 130, 8, (0, 16)),    # flagged antennas at both ends
+    (32, synth.FMT_CF32, 2, 40, 71, 3, (5,)),       # ragged last interval
+])
+def test_single_wave_solve(cuda, n, efmt, kernel, na, n_samples, t_cal, flagged):
+    """Arrays of at most 64 antennas with intervals of at most 8 samples are
+    solved by one wave per channel (DPP tap sums, no workgroup barriers)."""
+    wl = synth.config_small(n=n, efmt=efmt, kernel=kernel, n_ant=na, n_chan=3, n_samples=n_samples, t_cal=t_cal)
+    if flagged:
+        flags = np.zeros(na, np.uint8)
+        flags[list(flagged)] = 1
+        wl = wl.replace(array=synth.dataclasses.replace(wl.array, ant_flag=flags))
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+    if flagged:
+        f = np.array(flagged)
+        assert np.all(got["status"][:, f] & 1)
+        np.testing.assert_array_equal(got["gains"][:, f], wl.g0[:, f])
+
+
 def test_run_flagged_antennas(cuda):
     wl = synth.config_small(n_samples=150, t_cal=50)
     flags = np.zeros(wl.array.n_ant, np.uint8)

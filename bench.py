@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800",
-            "fetch_kib": 175015.9, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800",
-                      "fetch_kib": 237309.2, "fetch_scale": 2.000, "write_kib": 20480000.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "83d216d030f8ccec89ce599c178d2c9066f9d720538dc36964060d0f25a10034",
+            "fetch_kib": 175017.6, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "83d216d030f8ccec89ce599c178d2c9066f9d720538dc36964060d0f25a10034",
+                      "fetch_kib": 174307.7, "fetch_scale": 2.000, "write_kib": 20480043.3, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "9ae86a173526879e6e93892436eb9d8700258510e5ccb6422235be240b76c800", "valu_issue_frac": 0.49, "lds_busy_frac": 0.51},
+    "lwa": {"sources_sha256": "83d216d030f8ccec89ce599c178d2c9066f9d720538dc36964060d0f25a10034", "valu_issue_frac": 0.49, "lds_busy_frac": 0.51},
 }
 
 

@@ -1110,6 +1110,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
     const int j0 = plan->arrays[0].h.na > 1024 ? 2 : 1, ps0 = solve_ps(plan->arrays[0].h);
     for (int i = 1; i < na_arr; ++i)
       same = same && (plan->arrays[i].h.na > 1024 ? 2 : 1) == j0 && solve_ps(plan->arrays[i].h) == ps0;
+    for (int i = 0; i < na_arr; ++i) same = same && !epic::solve_by_wave(sa[i]);
     if (same) {
       epic::BatchSolveArgs b{};
       b.n_arrays = na_arr;

@@ -199,6 +199,9 @@ hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, do
                          float* image, hipStream_t s);
 bool solve_supported(int na, int fmt, int n_pix = 1);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// The solve of these arrays runs one wave per channel (small arrays, short
+// intervals): launch_solve picks it, so a batched solve leaves them to it.
+bool solve_by_wave(const SolveArgs& a);
 bool band_supported(int na, int fmt);
 // cooperative launch; *groups receives the number of workgroups
 hipError_t launch_solve_band(const BandArgs& b, int n_cu, hipStream_t s, int* groups = nullptr);

@@ -86,9 +86,13 @@ static hipError_t launch_solve_j(const SolveArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool solve_by_wave(const SolveArgs& a) {
+  return a.Na <= kSolveWaveMaxAnt && a.n_pix == 1 && a.t_cal <= kSolveWaveMaxTcal;
+}
+
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   if (!solve_supported(a.Na, a.fmt, a.n_pix)) return hipErrorInvalidValue;
-  if (a.Na <= kSolveWaveMaxAnt && a.n_pix == 1 && a.t_cal <= kSolveWaveMaxTcal) {
+  if (solve_by_wave(a)) {
     hipLaunchKernelGGL(k_solve_wave, dim3(a.F), dim3(64), 0, s, a);
     return hipGetLastError();
   }

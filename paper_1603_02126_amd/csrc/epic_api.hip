@@ -1378,7 +1378,8 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   hipError_t e = epic::launch_recip(reinterpret_cast<const double2*>(gains), ap.d_flag, h.F, h.na, u, s);
   if (e != hipSuccess) return hip_fail(e, "reciprocal launch");
   epic::AdjointArgs a{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, dL_dI, ap.d_slots,
-                      ap.n_slots, ap.d_cell_ixy, ap.d_cell_w, h.k2, splits, partial};
+                      ap.n_slots, ap.d_cell_ixy, ap.d_cell_w, h.k2, splits, partial,
+                      ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
   {
     Timed tm(plan, EPIC_TIMER_ADJOINT, s);
     e = epic::launch_adjoint(h.nx, a, s);

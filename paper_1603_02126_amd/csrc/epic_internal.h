@@ -127,6 +127,9 @@ struct AdjointArgs {
   int k2;
   int splits;
   double2* partial;         // [splits][F][Na]
+  // half-frame schedules (64 x 64 two-waves-per-SIMD engine), as in ImageArgs
+  const uint2* slots_h = nullptr;
+  int n_slots_h0 = 0, n_slots_h1 = 0;
 };
 
 // Batched execution over several arrays (one launch per stage).

@@ -34,12 +34,29 @@ def _oracle_grad(wl, packed, g, M, channels):
     return np.array(out)
 
 
-@pytest.mark.parametrize("n,na,efmt,kernel", [(32, 48, synth.FMT_CI8, 2), (64, 200, synth.FMT_CI4, 2),
-                                               (16, 30, synth.FMT_CF32, 1)])
-def test_adjoint_matches_oracle_gradient(cuda, n, na, efmt, kernel):
+def _edge_layout(wl, seed=5):
+    """Kernels that straddle columns 31/32 or wrap around the last column and
+    row (the paired adjoint degrids each half of the columns separately)."""
+    a = wl.array
+    na = a.n_ant
+    rng = np.random.default_rng(seed)
+    k = na // 3
+    px = np.concatenate([rng.uniform(31.0, 32.0, k), rng.uniform(63.0, 64.0, k), rng.uniform(5.0, 58.0, na - 2 * k)])
+    py = np.concatenate([rng.uniform(3.0, 60.0, 2 * k), rng.uniform(63.0, 64.0, na - 2 * k)])
+    xy = np.column_stack([a.x0 + px * a.dx, a.y0 + py * a.dy])
+    return wl.replace(array=synth.dataclasses.replace(a, ant_xy=xy))
+
+
+@pytest.mark.parametrize("n,na,efmt,kernel,edges", [(32, 48, synth.FMT_CI8, 2, False), (64, 200, synth.FMT_CI4, 2, False),
+                                                     (16, 30, synth.FMT_CF32, 1, False),
+                                                     (64, 180, synth.FMT_CI8, 1, False),
+                                                     (64, 150, synth.FMT_CI4, 2, True)])
+def test_adjoint_matches_oracle_gradient(cuda, n, na, efmt, kernel, edges):
     import torch
     from paper_1603_02126_amd.autograd import epic_image
     wl = synth.config_small(n=n, n_ant=na, efmt=efmt, kernel=kernel, n_chan=2, n_samples=53)
+    if edges:
+        wl = _edge_layout(wl)
     plan, packed, e, g = _setup(wl)
     M = np.random.default_rng(3).uniform(0, 1, size=(2, n, n)) * 0.5
     gt = torch.from_numpy(g.astype(np.complex64)).to(cuda).requires_grad_(True)

@@ -653,7 +653,7 @@ def bench_diff(args, dev):
     a = wl.array
     print(f"# generating {describe(wl)}", file=sys.stderr, flush=True)
     packed = synth.make_efield(wl, threads=min(16, os.cpu_count() or 1))
-    plan = new_plan([wl])
+    plan = new_plan([wl], {lib.OPT_SPLITS: args.splits} if args.splits else None)
     e = torch.from_numpy(packed).to(dev)
     g = torch.from_numpy(wl.g0).to(dev)
     M_np = np.random.default_rng(5).uniform(0, 1, size=(a.n_chan, a.ny, a.nx))

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the calibrated EPIC loop on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwa|hera|uneven|diff|tiny]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lwa|lwa_band|hera|uneven|diff|tiny]
 
 A step is one pass of the whole hot path over one batch of synthetic input:
 EPICal calibration solve (tap, correlation, damped FP64 update every t_cal

@@ -141,12 +141,19 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
 // ---------------------------------------------------------------------------
 constexpr int kClsPairThreads = 512;
 
-template <int R>
+// DB: the staged E' is double buffered (two pairs of frames; arrays of at
+// most kClsPairMaxAntDB antennas), so that no workgroup barrier has to keep a
+// pair's E' alive until every wave has gridded it: one barrier per pair of
+// samples instead of two.
+constexpr int kClsPairMaxAntDB = 384;
+
+template <int R, bool DB = false>
 struct ClsPairSmem {
   static constexpr int N = 64 * R;
   static constexpr int HALF = 64 * kHalfPitch;                   // float2 per wave
+  static constexpr int MAXA = DB ? kClsPairMaxAntDB : kClsMaxAnt;   // E' per frame
   static constexpr int E_OFF = 8 * HALF * 8;                     // bytes
-  static constexpr int TW_OFF = E_OFF + 2 * kClsMaxAnt * 8;
+  static constexpr int TW_OFF = E_OFF + (DB ? 4 : 2) * MAXA * 8;
   static constexpr int T_OFF = TW_OFF + N * 8;
   static constexpr int TAB_SLOTS = (kLdsBytes - T_OFF) / (64 * 8);
   static constexpr int BYTES = T_OFF + TAB_SLOTS * 64 * 8;
@@ -191,18 +198,18 @@ __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, cons
   }
 }
 
-template <int R, int FMT>
+template <int R, int FMT, bool DB>
 __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
   constexpr int N = 64 * R, NF = 64;
-  using L = ClsPairSmem<R>;
+  using L = ClsPairSmem<R, DB>;
   float2* lds = reinterpret_cast<float2*>(smem);
   const int tid = threadIdx.x, lam = tid & 63, wave = tid >> 6;
   const int fs = wave >> 2, ci = wave & 3;          // frame slot, class within the group
   const int c = cg * 4 + ci, cx = c % R, cy = c / R;
   const int gt = tid & 255;                         // thread within the frame's four waves
   float2* H = lds + wave * L::HALF;
-  float2* epr = reinterpret_cast<float2*>(smem + L::E_OFF) + fs * kClsMaxAnt;
+  float2* const e_base = reinterpret_cast<float2*>(smem + L::E_OFF);
   float2* tw = reinterpret_cast<float2*>(smem + L::TW_OFF);
   uint2* stab = reinterpret_cast<uint2*>(smem + L::T_OFF);
   const int S0 = a.n_slots_h0, S1 = a.n_slots_h1;
@@ -233,6 +240,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
   fetch_raw(tb + fs);
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t t = tb + 2 * it + fs;
+    float2* epr = e_base + ((DB ? int(it & 1) * 2 : 0) + fs) * L::MAXA;
     __builtin_amdgcn_s_setprio(1);   // LDS-bound phases at raised priority (see the 64 x 64 paired engine)
     // stage E' of this frame (its four waves)
     const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
@@ -255,7 +263,11 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     grid_cls_half<R, 4>(H, epr, tw, stab + S0 * 64, S1, 1, cx, cy, lam);
     wave_lds_sync();
     take_half_row<32>(v, H, lam);
-    __syncthreads();   // every wave is done with this pair's E'
+    // single buffer: every wave must be done with this pair's E' before the
+    // next pair is staged; double buffered, the next pair goes to the other
+    // buffer, and the pair after it is staged only after the barrier that
+    // follows the next staging, which every wave reaches after gridding this one
+    if constexpr (!DB) __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);
     __builtin_amdgcn_s_setprio(1);

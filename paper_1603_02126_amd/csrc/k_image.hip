@@ -74,12 +74,12 @@ __global__ __launch_bounds__(256) void k_image_cls(ImageArgs a) {
   image_cls_item<R, false>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
-template <int R, int FMT>
+template <int R, int FMT, bool DB>
 __global__ __launch_bounds__(kClsPairThreads) void k_image_cls_pair(ImageArgs a) {
-  __shared__ __align__(16) uint8_t smem[ClsPairSmem<R>::BYTES];
+  __shared__ __align__(16) uint8_t smem[ClsPairSmem<R, DB>::BYTES];
   constexpr int CG = (R * R) / 4;
   const int rest = blockIdx.x / a.F;
-  image_cls_pair_item<R, FMT>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
+  image_cls_pair_item<R, FMT, DB>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
 template <int R>
@@ -238,7 +238,14 @@ struct LaunchImage {
 };
 
 // The residue-class engine with two waves per SIMD: integer E-fields, at
-// most 512 antennas, half-frame schedules that fit its LDS table.
+// most 512 antennas, half-frame schedules that fit its LDS table; with at
+// most kClsPairMaxAntDB antennas and a table that still fits, its
+// double-buffered form (one barrier per pair of samples).
+static bool cls_pair_db(const ImageArgs& a, int N) {
+  const int cap = N == 128 ? ClsPairSmem<2, true>::TAB_SLOTS : ClsPairSmem<4, true>::TAB_SLOTS;
+  return a.Na <= kClsPairMaxAntDB && a.n_slots_h0 + a.n_slots_h1 <= cap;
+}
+
 bool cls_pair_engine(const ImageArgs& a, int N) {
   if (!(N == 128 || N == 256) || a.fmt == kCF32 || a.Na > kClsMaxAnt || !a.slots_h) return false;
   const int cap = N == 128 ? ClsPairSmem<2>::TAB_SLOTS : ClsPairSmem<4>::TAB_SLOTS;
@@ -251,10 +258,17 @@ hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
     const dim3 grid(a.F * (N == 256 ? 4 : 1) * a.splits);
     if (cls_pair_engine(a, N)) {
       const dim3 blk(kClsPairThreads);
-      if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<2, kCI4>), grid, blk, 0, s, a);
-      else if (N == 128) hipLaunchKernelGGL((k_image_cls_pair<2, kCI8>), grid, blk, 0, s, a);
-      else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<4, kCI4>), grid, blk, 0, s, a);
-      else hipLaunchKernelGGL((k_image_cls_pair<4, kCI8>), grid, blk, 0, s, a);
+      if (cls_pair_db(a, N)) {
+        if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<2, kCI4, true>), grid, blk, 0, s, a);
+        else if (N == 128) hipLaunchKernelGGL((k_image_cls_pair<2, kCI8, true>), grid, blk, 0, s, a);
+        else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<4, kCI4, true>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_image_cls_pair<4, kCI8, true>), grid, blk, 0, s, a);
+      } else {
+        if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<2, kCI4, false>), grid, blk, 0, s, a);
+        else if (N == 128) hipLaunchKernelGGL((k_image_cls_pair<2, kCI8, false>), grid, blk, 0, s, a);
+        else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_pair<4, kCI4, false>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_image_cls_pair<4, kCI8, false>), grid, blk, 0, s, a);
+      }
       return hipGetLastError();
     }
     if (N == 128 && !big) hipLaunchKernelGGL((k_image_cls<2>), grid, dim3(256), 0, s, a);

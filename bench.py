@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "01cf0fd1c87f108c8582eb5368fba03c6aebdb50c0fd21945bac46113e331392",
-            "fetch_kib": 175018.2, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "01cf0fd1c87f108c8582eb5368fba03c6aebdb50c0fd21945bac46113e331392",
-                      "fetch_kib": 174307.9, "fetch_scale": 2.000, "write_kib": 20480049.2, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d",
+            "fetch_kib": 175033.1, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d",
+                      "fetch_kib": 174308.1, "fetch_scale": 2.000, "write_kib": 20480052.9, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "01cf0fd1c87f108c8582eb5368fba03c6aebdb50c0fd21945bac46113e331392", "valu_issue_frac": 0.49, "lds_busy_frac": 0.51},
+    "lwa": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d", "valu_issue_frac": 0.50, "lds_busy_frac": 0.53},
 }
 
 

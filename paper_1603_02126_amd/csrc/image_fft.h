@@ -135,9 +135,9 @@ __device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t t
   fetch_raw(tb + wave);
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t t = tb + it * INFLIGHT + wave;
-    // the LDS-bound phases (staging, gridding, transpose) run at a raised
-    // wave priority so that they advance while the other wave of the SIMD
-    // is in an FFT
+    // the LDS-bound phases of staging and gridding run at a raised wave
+    // priority so that they advance while the other wave of the SIMD is in an
+    // FFT (raising it for the transpose as well measured slower)
     __builtin_amdgcn_s_setprio(1);
     // calibrate: all u loads are issued before any is used (one memory
     // latency per frame)
@@ -166,10 +166,8 @@ __device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t t
     wave_lds_sync();
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along x: lane = row y
-    __builtin_amdgcn_s_setprio(1);
-    transpose64(v, H, lam);       // lane = column kx
+    transpose64(v, H, lam);       // lane = column kx (normal priority: measured faster)
     static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
-    __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along y
     // the next frame's samples are requested here rather than at staging:
     // their registers would otherwise stay live through both FFTs
@@ -373,10 +371,8 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     wave_lds_sync();
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);
-    __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);
     static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
-    __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);
     SnapCursor nxt = cur;
     nxt.next();

@@ -200,6 +200,17 @@ __device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const
   }
 }
 
+// grid_frame with a batch that takes a short schedule in one pass: every
+// batch costs two LDS round trips, and the slots of a batch past S are loads
+// for nothing (a 9-slot half: one batch of 10 instead of two of 8).
+__device__ __forceinline__ void grid_frame_fit(float2* buf, const float2* epr, const uint2* stab, int S, int L,
+                                               int lam) {
+  if (S <= 8) grid_frame<8>(buf, epr, stab, S, L, lam);
+  else if (S <= 10) grid_frame<10>(buf, epr, stab, S, L, lam);
+  else if (S <= 12) grid_frame<12>(buf, epr, stab, S, L, lam);
+  else grid_frame<8>(buf, epr, stab, S, L, lam);
+}
+
 template <int N, int APL>
 __device__ __forceinline__ void fetch_frame(Raw (&raw)[APL], float2 (&uu)[APL], const uint8_t* efield,
                                             const float2* u, int64_t t, int64_t t_cal, int f, int F,

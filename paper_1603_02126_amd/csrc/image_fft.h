@@ -155,12 +155,12 @@ __device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t t
     });
     wave_lds_sync();
     // columns 0..31: grid, every lane loads its row's half and clears it
-    grid_frame<8>(H, epr, stab, S0, N, lam);
+    grid_frame_fit(H, epr, stab, S0, N, lam);
     wave_lds_sync();
     take_half_row<0>(v, H, lam);
     wave_lds_sync();
     // columns 32..63
-    grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
+    grid_frame_fit(H, epr, stab + S0 * N, S1, N, lam);
     wave_lds_sync();
     take_half_row<32>(v, H, lam);
     wave_lds_sync();
@@ -361,11 +361,11 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
       if (an < a.Na) epr[an] = cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, FMT), uu[decltype(ic)::value]);
     });
     wave_lds_sync();
-    grid_frame<8>(H, epr, stab, S0, N, lam);
+    grid_frame_fit(H, epr, stab, S0, N, lam);
     wave_lds_sync();
     take_half_row<0>(v, H, lam);
     wave_lds_sync();
-    grid_frame<8>(H, epr, stab + S0 * N, S1, N, lam);
+    grid_frame_fit(H, epr, stab + S0 * N, S1, N, lam);
     wave_lds_sync();
     take_half_row<32>(v, H, lam);
     wave_lds_sync();

@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d",
-            "fetch_kib": 175033.1, "fetch_scale": 2.000, "write_kib": 40960.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d",
-                      "fetch_kib": 174308.1, "fetch_scale": 2.000, "write_kib": 20480052.9, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4",
+            "fetch_kib": 175059.8, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4",
+                      "fetch_kib": 174328.7, "fetch_scale": 2.000, "write_kib": 20488240.7, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "9cf9032787be81fe73b0c118ab67fd40fca348ec8535f68981a42ee672befc1d", "valu_issue_frac": 0.50, "lds_busy_frac": 0.53},
+    "lwa": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
 }
 
 

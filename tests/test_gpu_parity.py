@@ -258,6 +258,44 @@ def test_paired_engine_half_frame_edges(cuda, layout):
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
 
 
+def _half_schedule_length(cells, nx, half):
+    """Longest lane of a half-frame gridding schedule: the cells of the half
+    (columns 32*half .. 32*half+31), largest first, each to the least-loaded of
+    64 lanes, a cell costing one slot per antenna that touches it."""
+    ix, iy, w = (np.asarray(v).ravel() for v in (cells.ix, cells.iy, cells.w))
+    keep = (w != 0) & (ix // 32 == half)
+    flat = iy[keep] * nx + ix[keep]
+    ids, counts = np.unique(flat, return_counts=True)
+    load = np.zeros(64, np.int64)
+    for k in np.argsort(-counts, kind="stable"):
+        load[np.argmin(load)] += counts[k]
+    return int(load.max())
+
+
+@pytest.mark.parametrize("na,lo,hi", [(129, 9, 10), (176, 11, 12), (250, 13, 20), (140, 1, 8)])
+def test_paired_engine_gridding_batch_lengths(cuda, na, lo, hi):
+    """The 64 x 64 paired engine grids each half in batches sized to the
+    half's schedule (8, 10 or 12 slots, batches of 8 beyond 12).  Antennas
+    packed into columns 0..31 give first-half schedules in each range; the
+    last case spreads them over both halves."""
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI8, n_ant=na, n_chan=2, n_samples=100, t_cal=50)
+    a = wl.array
+    rng = np.random.default_rng(na)
+    xmax = 62.0 if hi <= 8 else 30.0
+    p = np.column_stack([rng.uniform(1.0, xmax, na), rng.uniform(1.0, 62.0, na)])
+    xy = np.column_stack([a.x0 + p[:, 0] * a.dx, a.y0 + p[:, 1] * a.dy])
+    wl = wl.replace(array=synth.dataclasses.replace(a, ant_xy=xy))
+    cells = O.grid_cells(xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    s0 = _half_schedule_length(cells, a.nx, 0)
+    print(f"paired gridding: Na={na} first-half schedule {s0}", flush=True)
+    assert lo <= s0 <= hi
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
 @pytest.mark.parametrize("splits", [1, 3, 64])
 def test_run_split_counts_agree(cuda, splits):
     """Any time split of the imaging launch gives the same answer."""

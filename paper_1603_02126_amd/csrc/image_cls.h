@@ -198,6 +198,18 @@ __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, cons
   }
 }
 
+// grid_cls_half with the batch chosen from the half's schedule length: a
+// schedule of up to 12 slots goes in one batch (two LDS round trips) rather
+// than in three of 4.
+template <int R>
+__device__ __forceinline__ void grid_cls_half_fit(float2* H, const float2* epr, const float2* tw, const uint2* stab,
+                                                  int S, int hf, int cx, int cy, int lam) {
+  if (S <= 4) grid_cls_half<R, 4>(H, epr, tw, stab, S, hf, cx, cy, lam);
+  else if (S <= 8) grid_cls_half<R, 8>(H, epr, tw, stab, S, hf, cx, cy, lam);
+  else if (S <= 12) grid_cls_half<R, 12>(H, epr, tw, stab, S, hf, cx, cy, lam);
+  else grid_cls_half<R, 4>(H, epr, tw, stab, S, hf, cx, cy, lam);
+}
+
 template <int R, int FMT, bool DB>
 __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
@@ -256,11 +268,11 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
                                       : make_float2(0.f, 0.f);
     });
     __syncthreads();
-    grid_cls_half<R, 4>(H, epr, tw, stab, S0, 0, cx, cy, lam);
+    grid_cls_half_fit<R>(H, epr, tw, stab, S0, 0, cx, cy, lam);
     wave_lds_sync();
     take_half_row<0>(v, H, lam);
     wave_lds_sync();
-    grid_cls_half<R, 4>(H, epr, tw, stab + S0 * 64, S1, 1, cx, cy, lam);
+    grid_cls_half_fit<R>(H, epr, tw, stab + S0 * 64, S1, 1, cx, cy, lam);
     wave_lds_sync();
     take_half_row<32>(v, H, lam);
     // single buffer: every wave must be done with this pair's E' before the

@@ -258,11 +258,14 @@ def test_paired_engine_half_frame_edges(cuda, layout):
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
 
 
-def _half_schedule_length(cells, nx, half):
+def _half_schedule_length(cells, nx, half, fold=False):
     """Longest lane of a half-frame gridding schedule: the cells of the half
     (columns 32*half .. 32*half+31), largest first, each to the least-loaded of
-    64 lanes, a cell costing one slot per antenna that touches it."""
+    64 lanes, a cell costing one slot per antenna that touches it.  With fold,
+    the residue-class engines' schedule: cells taken modulo 64 in x and y."""
     ix, iy, w = (np.asarray(v).ravel() for v in (cells.ix, cells.iy, cells.w))
+    if fold:
+        ix, iy, nx = ix % 64, iy % 64, 64
     keep = (w != 0) & (ix // 32 == half)
     flat = iy[keep] * nx + ix[keep]
     ids, counts = np.unique(flat, return_counts=True)
@@ -289,6 +292,33 @@ def test_paired_engine_gridding_batch_lengths(cuda, na, lo, hi):
     s0 = _half_schedule_length(cells, a.nx, 0)
     print(f"paired gridding: Na={na} first-half schedule {s0}", flush=True)
     assert lo <= s0 <= hi
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
+@pytest.mark.parametrize("n,na,left,lo,hi", [(128, 60, False, 1, 4), (128, 200, False, 5, 8), (128, 340, False, 9, 12),
+                                            (128, 250, True, 13, 20), (256, 340, False, 9, 12)])
+def test_class_pair_engine_gridding_batch_lengths(cuda, n, na, left, lo, hi):
+    """The residue-class engine with two waves per SIMD grids each half of a
+    class in batches sized to the half's schedule (4, 8 or 12 slots, batches
+    of 4 beyond 12).  'left' puts every antenna in folded columns 0..31."""
+    wl = synth.config_small(n=n, efmt=synth.FMT_CI8, kernel=2, n_ant=na, n_chan=2, n_samples=60, t_cal=30)
+    a = wl.array
+    rng = np.random.default_rng(na + n)
+    if left:
+        px = rng.uniform(1.0, 30.0, na) + 64.0 * rng.integers(0, n // 64, na)
+    else:
+        px = rng.uniform(1.0, n - 2.0, na)
+    p = np.column_stack([px, rng.uniform(1.0, n - 2.0, na)])
+    xy = np.column_stack([a.x0 + p[:, 0] * a.dx, a.y0 + p[:, 1] * a.dy])
+    wl = wl.replace(array=synth.dataclasses.replace(a, ant_xy=xy))
+    cells = O.grid_cells(xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    s0, s1 = (_half_schedule_length(cells, a.nx, h, fold=True) for h in (0, 1))
+    print(f"class-pair gridding: N={n} Na={na} half schedules {s0}, {s1}", flush=True)
+    assert lo <= s0 <= hi and s0 + s1 <= 26
     packed = synth.make_efield(wl)
     ref = oracle_run(wl, packed)
     got = gpu_run(wl, packed, cuda)

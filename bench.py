@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4",
-            "fetch_kib": 175059.8, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4",
-                      "fetch_kib": 174328.7, "fetch_scale": 2.000, "write_kib": 20488240.7, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "e35dbe2f0f46fd6457a439e6662d3257dbd4c972be5dca2d04ae522566a2d93b",
+            "fetch_kib": 175059.0, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "e35dbe2f0f46fd6457a439e6662d3257dbd4c972be5dca2d04ae522566a2d93b",
+                      "fetch_kib": 174337.5, "fetch_scale": 2.000, "write_kib": 20488230.2, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "3c0cbb0d2b35d072e5d0f406d5bc1983660b570ce690f4be25b67d2d184aa8a4", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "e35dbe2f0f46fd6457a439e6662d3257dbd4c972be5dca2d04ae522566a2d93b", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
 }
 
 

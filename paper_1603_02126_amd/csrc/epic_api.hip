@@ -968,7 +968,9 @@ static int solve_ps(const HostArray& h) {
 
 // Arrays whose FFT engine has a two-waves-per-SIMD form (512-thread
 // workgroups) are imaged by their own launch in the batched form: the
-// persistent kernel runs 256-thread engine bodies.
+// persistent kernel runs 256-thread engine bodies.  So are the dense class
+// arrays (slot table in memory): their own kernel grids in batches of slots,
+// which the persistent kernel's body does not (there it measured slower).
 static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
   const int code = engine_of(plan, ap), N = ap.h.nx;
   ImageArgs ia{};
@@ -979,6 +981,7 @@ static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
   ia.n_slots_h1 = ap.n_slots_h1;
   if (code / 100 == epic::kEngFft) return epic::pair_engine(ia, N);
   if (code / 100 == epic::kEngCls) return epic::cls_pair_engine(ia, N);
+  if (code / 100 == epic::kEngClsBig) return true;
   return false;
 }
 
@@ -1141,8 +1144,9 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       if (e != hipSuccess) return hip_fail(e, "gain history conversion launch");
     }
   }
-  // imaging: the arrays with a two-waves-per-SIMD engine by their own
-  // launches, the others by one persistent launch over their work items
+  // imaging: the arrays with a two-waves-per-SIMD engine or a dense class
+  // engine by their own launches, the others by one persistent launch over
+  // their work items
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     for (int i = 0; i < na_arr; ++i) {

@@ -25,6 +25,7 @@
 namespace epic {
 
 constexpr int kClsMaxAnt = 512;
+constexpr int kClsGridBatch = 8;   // gridding slots per batch in the one-wave class engines
 constexpr int kClsMaxAntBig = 2048;
 constexpr int kClsTabSlots =
     (kLdsBytes - 4 * Geo<64>::FRAME * 8 - 2 * kClsMaxAnt * 8 - 256 * 8) / (64 * 8);
@@ -40,7 +41,9 @@ struct ClsSmem {
 };
 
 // One work item: channel f, class group cg (four classes), time split s.
-template <int R, bool BIG>
+// GB: gridding slots per batch; 0 grids one slot at a time (the persistent
+// multi-array kernel, where that form measured faster).
+template <int R, bool BIG, int GB = kClsGridBatch>
 __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
   constexpr int N = 64 * R;
   constexpr int MAXI = BIG ? kClsMaxAntBig / 256 : kClsMaxAnt / 256;   // antennas per thread
@@ -97,20 +100,48 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
     __syncthreads();
     // grid class (cx, cy): owned sub-cells, each contribution phased by exp(+2 pi i j.c / N)
     float2 sum = make_float2(0.f, 0.f);
+    if constexpr (GB > 0) {
+      // slots in batches: the batch's table entries are all requested before the
+      // first is used (from memory for the dense variant), so one wait covers them
+      const int S = a.n_slots;
+      for (int k0 = 0; k0 < S; k0 += GB) {
+        uint2 e[GB];
+        static_for<0, GB>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const int k = k0 + j < S ? k0 + j : S - 1;
+          e[j] = BIG ? gload(a.slots + k * 64 + lane) : stab[k * 64 + lane];
+        });
+        static_for<0, GB>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const uint32_t code = e[j].x;
+          const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
+          const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
+          const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
+          const float w = __uint_as_float(e[j].y);
+          const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
+          const bool first = int(code) < 0;
+          sum.x = first ? ev.x : sum.x + ev.x;
+          sum.y = first ? ev.y : sum.y + ev.y;
+          const int off = (code >> 30) & 1 ? qy * P + qx : 64;
+          if (k0 + j < S) buf[off] = sum;
+        });
+      }
+    } else {
 #pragma unroll 4
-    for (int k = 0; k < a.n_slots; ++k) {
-      const uint2 e = BIG ? gload(a.slots + k * 64 + lane) : stab[k * 64 + lane];
-      const uint32_t code = e.x;
-      const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
-      const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
-      const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
-      const float w = __uint_as_float(e.y);
-      const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
-      const bool first = int(code) < 0;
-      sum.x = first ? ev.x : sum.x + ev.x;
-      sum.y = first ? ev.y : sum.y + ev.y;
-      const int off = (code >> 30) & 1 ? qy * P + qx : 64;
-      buf[off] = sum;
+      for (int k = 0; k < a.n_slots; ++k) {
+        const uint2 e = BIG ? gload(a.slots + k * 64 + lane) : stab[k * 64 + lane];
+        const uint32_t code = e.x;
+        const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
+        const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
+        const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
+        const float w = __uint_as_float(e.y);
+        const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
+        const bool first = int(code) < 0;
+        sum.x = first ? ev.x : sum.x + ev.x;
+        sum.y = first ? ev.y : sum.y + ev.y;
+        const int off = (code >> 30) & 1 ? qy * P + qx : 64;
+        buf[off] = sum;
+      }
     }
     if constexpr (BIG) __syncthreads();   // the single staging buffer is rewritten next
     else wave_lds_sync();

@@ -46,7 +46,7 @@ __device__ __noinline__ void dft_call(const ImageArgs& a, int4 w, uint8_t* smem)
 template <int R, bool BIG>
 __device__ __noinline__ void cls_call(const ImageArgs& a, int4 w, uint8_t* smem) {
   const ImageArgs la = a;
-  image_cls_item<R, BIG>(la, w.y, w.z, w.w, smem);
+  image_cls_item<R, BIG, 0>(la, w.y, w.z, w.w, smem);
 }
 
 // engine code: 100 * engine + N / 32 * 10 + param (APL or R)

@@ -19,6 +19,9 @@
  *     enqueued on `stream` has finished.  Device work is asynchronous on
  *     `stream` (a hipStream_t; NULL = the null stream); argument checks are
  *     synchronous and happen before anything is enqueued.
+ *   - Every device buffer a call takes starts on a 256-byte boundary (torch
+ *     allocations do; a view that starts inside an allocation may not):
+ *     EPIC_ERR_ARG otherwise.
  *   - Complex numbers are interleaved (re, im) pairs of the stated real type.
  *   - Array layouts are C order (last index fastest); sizes are elements.
  *   - E-field streams are [T][F][Na] packed samples in the array's format.
@@ -69,7 +72,11 @@ typedef enum {
  * kernel 1 = nearest cell, jx = floor((x - x0)/dx + 0.5);
  * kernel 2 = 2x2 bilinear (area overlap of a one-cell tophat):
  *   i0 = floor(p), phi = p - i0, weights (1-phi, phi) per axis.
- * nx == ny, a power of two in {16, 32, 64, 128}. */
+ * The imaging calls take nx == ny, a power of two in {16, 32, 64, 128, 256}:
+ * Na <= 8 nx for nx <= 64 (and a gridding schedule that fits the LDS slot
+ * table: at 64 x 64, 512 antennas fit with kernel 1 but not kernel 2),
+ * Na <= 2048 for 128 and 256.  The stage-wise calls and the adjoint take
+ * grids up to 64 x 64.  Other shapes give EPIC_ERR_UNSUPPORTED. */
 typedef struct {
   int32_t n_ant;           /* Na >= 1 */
   int32_t n_chan;          /* F >= 1 */
@@ -214,6 +221,19 @@ int epical_set_model_pixels(epic_plan_t plan, int32_t array, const epic_model_de
 int epical_set_band(epic_plan_t plan, int32_t array, int32_t b0, int32_t b1, int32_t mode, int32_t deg_amp,
                     int32_t deg_phase);
 
+/* Caller-supplied model denominator (eq. cal_solution: D_a = sum_{b != a}
+ * conj(W_b(s0)) V^M_ab, which Sec. 2.2 notes is computed before observing,
+ * from whatever model of the sky the caller holds), in place of the one
+ * epical_set_model derives from its point-source list.  Needs a prior
+ * epical_set_model / epical_set_model_pixels call, which fixes the tapped
+ * pixels, A, gamma and t_cal (EPIC_ERR_STATE otherwise).
+ *   D: host [n_pix][F][Na] complex128 (n_pix of that call, 1 for
+ *      epical_set_model), finite (EPIC_ERR_ARG otherwise); copied.
+ * The hold rule is re-derived from D: an antenna whose sum_p |D_ap|^2 is at
+ * most 1e-24 of the channel's largest (|D_a| <= 1e-12 max|D| for one pixel)
+ * is held; flagged antennas stay held.  Waits for the device. */
+int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
+
 /* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)
  *   EPIC_OPT_TRANSFORM   0 = FFT, 1 = FFT (FP32), 2 = DFT-GEMM (FP16 hi+lo split on
@@ -265,6 +285,21 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
 int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning);
 int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning);
 int epic_plan_get_timing(epic_plan_t plan, double* ms, int64_t* launches, int32_t n);
+
+/* Read back the plan's device gridding tables of one array (eq. gridding):
+ * ixy host [Na][K][2] int32 (jx, jy) after the modulo wrap, w host [Na][K]
+ * float32 kernel weights as the device holds them, K = 1 (kernel 1) or 4
+ * (kernel 2) in the cell order of epic_host_grid_cells.  Flagged antennas
+ * carry weight 0 (they are not gridded).  Synchronous. */
+int epic_plan_get_cells(epic_plan_t plan, int32_t array, int32_t* ixy, float* w);
+
+/* Decode n packed integer samples (the F-engine output, Sec. 2.1) with the
+ * imaging engines' own unpacking, for checking it:
+ *   out[i] = (re, im) of sample i of `efield`, as int16.
+ * efield: device, n samples in the array's format (EPIC_CI4 or EPIC_CI8;
+ * EPIC_CF32 gives EPIC_ERR_UNSUPPORTED); out: device [n][2] int16. */
+int epic_debug_unpack(epic_plan_t plan, int32_t array, const void* efield, int64_t n, int16_t* out,
+                      epic_stream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* Stage-wise calls (each stage of the loop on its own, through HBM)       */

@@ -655,6 +655,26 @@ def image_fixed_gains(E: np.ndarray, g: np.ndarray, cells: GridCells, nx, ny, na
     return (np.abs(X) ** 2).mean(axis=0)
 
 
+def model_image(cells: GridCells, nx, ny, na, ant_xy, freq, src_lmS, sigma: float) -> np.ndarray:
+    """The expected time-averaged image (Sec. 2.1, squared and averaged in
+    time) of a point-source sky with receiver noise, at exact gains:
+    <E'_a E'*_b> = V^M_ab + sigma delta_ab gives
+
+        M_k = sum_s S_s |(1/Na) sum_a A_a(k) e_a(s)|^2 + (sigma / Na^2) sum_a |A_a(k)|^2,
+
+    e_a(s) = exp(-2 pi i f r_a . s_s / c), A_a(k) the gridded antenna's
+    response at pixel k.  (1/Na) sum_a A_a(k) e_a(s) is the transform of the
+    grid of e(s), and A_a(k) / Na that of antenna a's grid alone."""
+    ant_xy = np.asarray(ant_xy, np.float64)
+    n_ant = ant_xy.shape[0]
+    M = np.zeros((ny, nx), np.float64)
+    for l, m, S in np.asarray(src_lmS, np.float64):
+        e = np.exp(-2j * np.pi * freq * (ant_xy[:, 0] * l + ant_xy[:, 1] * m) / C_LIGHT)
+        M += S * np.abs(dft2(grid(e[None, :], cells, nx, ny), na)[0]) ** 2
+    X = dft2(grid(np.eye(n_ant, dtype=np.complex128), cells, nx, ny), na)
+    return M + sigma * (np.abs(X) ** 2).sum(axis=0)
+
+
 def image_gain_gradient(E, g, cells: GridCells, nx, ny, na, R, flags=None):
     """Gradient of a real loss L(I') with respect to the complex gains, given
     R = dL/dI' [ny, nx].

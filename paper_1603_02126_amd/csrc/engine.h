@@ -101,11 +101,6 @@ __device__ __forceinline__ float2 load_sample_global(const uint8_t* row, int a, 
   return unpack_raw(load_raw_global(row, a, fmt), fmt);
 }
 
-__device__ __forceinline__ void lds_add(float2* p, float2 v) {
-  __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // Order LDS traffic of one wavefront: the hardware executes a wave's LDS
 // instructions in order; this keeps the compiler from moving them across.
 __device__ __forceinline__ void wave_lds_sync() {

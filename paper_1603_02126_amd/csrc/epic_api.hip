@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <limits>
 #include <string>
 #include <vector>
@@ -411,6 +412,7 @@ struct epic_plan_s {
   size_t items_cap = 0;
   int n_items = 0;
   std::vector<int> items_key;
+  bool items_built = false;
   int* d_counter = nullptr;
   // captured graph and the private stream it runs on
   hipStream_t gstream = nullptr;
@@ -473,6 +475,16 @@ int check_plan(epic_plan_t p, int array) {
   int dev = -1;
   hipGetDevice(&dev);
   if (dev != p->device) return fail(EPIC_ERR_ARG, "current device %d is not the plan's device %d", dev, p->device);
+  return EPIC_OK;
+}
+
+// Caller buffers on the device start on a 256-byte boundary (the boundary's
+// contract; torch allocations do).  Null pointers pass (optional buffers are
+// checked for presence separately).
+int check_aligned(std::initializer_list<std::pair<const void*, const char*>> bufs) {
+  for (const auto& b : bufs)
+    if (b.first && (reinterpret_cast<uintptr_t>(b.first) & 255u) != 0)
+      return fail(EPIC_ERR_ARG, "%s (%p) is not 256-byte aligned", b.second, b.first);
   return EPIC_OK;
 }
 
@@ -806,16 +818,95 @@ int epical_set_band(epic_plan_t plan, int32_t array, int32_t b0, int32_t b1, int
   return EPIC_OK;
 }
 
+int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  ArrayPlan& ap = plan->arrays[array];
+  if (!ap.has_model) return fail(EPIC_ERR_STATE, "epical_set_model has not been called for array %d", array);
+  if (!D) return fail(EPIC_ERR_ARG, "D must not be NULL");
+  const HostArray& h = ap.h;
+  const size_t FN = size_t(h.F) * h.na, n = FN * ap.n_pix;
+  for (size_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(D[i])) return fail(EPIC_ERR_ARG, "D must be finite");
+  // hold bits as epical_set_model derives them: flagged, or sum_p |D_ap|^2 at
+  // most 1e-24 of its largest value over the channel's antennas
+  std::vector<uint8_t> hold(FN, 0);
+  std::vector<double> den(h.na);
+  for (int f = 0; f < h.F; ++f) {
+    for (int a = 0; a < h.na; ++a) {
+      double d = 0;
+      for (int p = 0; p < ap.n_pix; ++p) {
+        const double* z = D + 2 * (size_t(p) * FN + size_t(f) * h.na + a);
+        d += z[0] * z[0] + z[1] * z[1];
+      }
+      den[a] = d;
+    }
+    const double dmax = *std::max_element(den.begin(), den.end());
+    for (int a = 0; a < h.na; ++a) {
+      uint8_t hb = h.flag[a] ? epic::kHoldFlagged : 0;
+      if (!(den[a] > 1e-24 * dmax)) hb |= epic::kHoldDZero;
+      hold[size_t(f) * h.na + a] = hb;
+    }
+  }
+  // runs still in flight read the old tables
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(ap.d_D, D, n * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ap.d_hold, hold.data(), FN, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "denominator upload");
+  plan->generation++;
+  return EPIC_OK;
+}
+
+int epic_plan_get_cells(epic_plan_t plan, int32_t array, int32_t* ixy, float* w) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  if (!ixy || !w) return fail(EPIC_ERR_ARG, "ixy and w must not be NULL");
+  const ArrayPlan& ap = plan->arrays[array];
+  const size_t na = size_t(ap.h.na);
+  std::vector<uint32_t> cells(na * 4);
+  std::vector<float> wt(na * 4);
+  hipError_t e = hipMemcpy(cells.data(), ap.d_cell_ixy, cells.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(wt.data(), ap.d_cell_w, wt.size() * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "cell table read-back");
+  const int k2 = ap.h.k2;
+  for (size_t a = 0; a < na; ++a)
+    for (int k = 0; k < k2; ++k) {
+      const uint32_t c = cells[4 * a + k];
+      ixy[2 * (a * k2 + k)] = int32_t(c & 0xffffu);
+      ixy[2 * (a * k2 + k) + 1] = int32_t(c >> 16);
+      w[a * k2 + k] = wt[4 * a + k];
+    }
+  return EPIC_OK;
+}
+
+int epic_debug_unpack(epic_plan_t plan, int32_t array, const void* efield, int64_t n, int16_t* out,
+                      epic_stream_t stream) {
+  int rc = check_plan(plan, array);
+  if (rc) return rc;
+  const ArrayPlan& ap = plan->arrays[array];
+  if (ap.h.efmt != EPIC_CI4 && ap.h.efmt != EPIC_CI8)
+    return fail(EPIC_ERR_UNSUPPORTED, "epic_debug_unpack decodes the integer formats (ci4, ci8) only");
+  if (n < 0) return fail(EPIC_ERR_ARG, "n must be >= 0");
+  if (n > 0 && (!efield || !out)) return fail(EPIC_ERR_ARG, "efield and out must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {out, "out"}}))) return rc;
+  hipError_t e = epic::launch_unpack(static_cast<const uint8_t*>(efield), n, ap.h.efmt, out,
+                                     static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "epic_debug_unpack launch");
+}
+
 int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
   if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
   switch (key) {
+    // options that change the launches a run records retire its captured graph
     case EPIC_OPT_SPLITS:
       if (value < 0 || value > (1 << 20)) return fail(EPIC_ERR_ARG, "splits out of range");
       plan->splits = int(value);
+      plan->generation++;
       return EPIC_OK;
     case EPIC_OPT_TRANSFORM:
       if (value < 0 || value > 2) return fail(EPIC_ERR_ARG, "transform must be 0, 1 or 2");
       plan->transform = int(value);
+      plan->generation++;
       return EPIC_OK;
     case EPIC_OPT_TIMING:
       plan->timing = value != 0;
@@ -823,6 +914,7 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
     case EPIC_OPT_BATCH:
       if (value < 0 || value > 2) return fail(EPIC_ERR_ARG, "batch must be 0 (auto), 1 (on) or 2 (off)");
       plan->batch = int(value);
+      plan->generation++;
       return EPIC_OK;
     case EPIC_OPT_GRAPH:
       plan->graph = value != 0;
@@ -864,6 +956,7 @@ int epic_grid(epic_plan_t plan, int32_t array, const void* efield, int64_t t0, i
   if ((rc = check_grid_supported(ap, true))) return rc;
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (nt > 0 && (!efield || !u || !grid)) return fail(EPIC_ERR_ARG, "efield, u and grid must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {u, "u"}, {grid, "grid"}}))) return rc;
   epic::GridArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
                    reinterpret_cast<const float2*>(u), ap.d_slots, ap.n_slots, reinterpret_cast<float2*>(grid)};
   hipError_t e = epic::launch_grid(ap.h.nx, a, static_cast<hipStream_t>(stream));
@@ -879,6 +972,7 @@ int epic_image_accumulate(epic_plan_t plan, int32_t array, const float* grid, in
   if (nt < 0) return fail(EPIC_ERR_ARG, "nt must be >= 0");
   if (nt > 0 && (!grid || !image)) return fail(EPIC_ERR_ARG, "grid and image must not be NULL");
   if (tap && !ap.has_model) return fail(EPIC_ERR_STATE, "tap requested but no model (calibrator pixel) set");
+  if ((rc = check_aligned({{grid, "grid"}, {image, "image"}, {tap, "tap"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   epic::ImageAccArgs a{reinterpret_cast<const float2*>(grid), nt, ap.h.F, float(1.0 / ap.h.na_eff), image,
                        reinterpret_cast<float2*>(tap), tap ? ap.d_k0 : nullptr};
@@ -901,6 +995,8 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
   if (nt < 0 || t0 < 0) return fail(EPIC_ERR_ARG, "t0 and nt must be >= 0");
   if (!kq || !gains) return fail(EPIC_ERR_ARG, "kq and gains must not be NULL");
   if (nt > 0 && (!efield || !tap)) return fail(EPIC_ERR_ARG, "efield and tap must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {tap, "tap"}, {kq, "kq"}, {gains, "gains"}, {status, "status"}})))
+    return rc;
   epic::UpdateArgs a{static_cast<const uint8_t*>(efield), t0, nt, ap.h.F, ap.h.na, ap.h.efmt,
                      reinterpret_cast<const float2*>(tap), kq, reinterpret_cast<double2*>(gains), ap.d_A, ap.d_D,
                      ap.d_hold, double(ap.h.na_eff), ap.gamma, finalize ? 1 : 0, status};
@@ -981,7 +1077,7 @@ static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
   ia.n_slots_h1 = ap.n_slots_h1;
   if (code / 100 == epic::kEngFft) return epic::pair_engine(ia, N);
   if (code / 100 == epic::kEngCls) return epic::cls_pair_engine(ia, N);
-  if (code / 100 == epic::kEngClsBig) return true;
+  if (code / 100 == epic::kEngClsBig || code / 100 == epic::kEngDftCls) return true;
   return false;
 }
 
@@ -991,7 +1087,7 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   std::vector<int> key{int(n_samples & 0x7fffffff), int(n_samples >> 31)};
   for (size_t i = 0; i < lay.size(); ++i) key.push_back(lay[i].splits);
   for (size_t i = 0; i < lay.size(); ++i) key.push_back(own_launch(plan, plan->arrays[i]) ? 1 : 0);
-  if (key == plan->items_key && plan->d_items) return EPIC_OK;
+  if (plan->items_built && key == plan->items_key) return EPIC_OK;
   struct It {
     int4 w;
     double cost;
@@ -1011,6 +1107,14 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   std::stable_sort(items.begin(), items.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
   std::vector<int4> w(items.size());
   for (size_t k = 0; k < items.size(); ++k) w[k] = items[k].w;
+  // A launch of an earlier call may still be reading the list, on any stream
+  // (the caller's, or the plan's graph stream): drain the device before the
+  // list is rewritten, and retire every graph that captured the old one.
+  if (plan->d_items) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before the work list upload");
+  }
+  plan->generation++;
   if (w.size() > plan->items_cap) {
     hipFree(plan->d_items);
     plan->d_items = nullptr;
@@ -1018,7 +1122,6 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
     if (hipMalloc(&plan->d_items, w.size() * sizeof(int4)) != hipSuccess)
       return fail(EPIC_ERR_ALLOC, "work list allocation failed");
     plan->items_cap = w.size();
-    plan->generation++;
   }
   if (!w.empty()) {
     hipError_t e = hipMemcpy(plan->d_items, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice);
@@ -1026,6 +1129,7 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   }
   plan->n_items = int(w.size());
   plan->items_key = key;
+  plan->items_built = true;
   return EPIC_OK;
 }
 
@@ -1153,11 +1257,12 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       ArrayPlan& ap = plan->arrays[i];
       if (!own_launch(plan, ap)) continue;
       const HostArray& h = ap.h;
+      const bool dft = engine_of(plan, ap) / 100 == epic::kEngDftCls;
       ImageArgs ia{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt,
                    reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal, ap.d_slots, ap.n_slots,
                    lay[i].splits, reinterpret_cast<float*>(scr + lay[i].p_off), ap.d_slots_h, ap.n_slots_h0,
                    ap.n_slots_h1};
-      hipError_t e = epic::launch_image(h.nx, ia, s);
+      hipError_t e = dft ? epic::launch_image_dft(h.nx, ia, s) : epic::launch_image(h.nx, ia, s);
       if (e != hipSuccess) return hip_fail(e, "imaging launch");
     }
   }
@@ -1221,6 +1326,10 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     if (!epic::solve_supported(ap.h.na, ap.h.efmt, ap.n_pix))
       return fail(EPIC_ERR_UNSUPPORTED, "calibration solve supports Na <= 2048 and Na * bytes per sample <= 16 KiB");
     if (!efield[i] || !gains[i] || !image[i]) return fail(EPIC_ERR_ARG, "NULL buffer for array %d", i);
+    if ((rc = check_aligned({{efield[i], "efield"}, {gains[i], "gains"}, {image[i], "image"},
+                             {gain_hist ? gain_hist[i] : nullptr, "gain_hist"},
+                             {ant_status ? ant_status[i] : nullptr, "ant_status"}})))
+      return rc;
     rc = layout_array(ap, n_samples, pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits),
                       size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
@@ -1315,6 +1424,9 @@ int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int6
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   if (t_acc < 1) return fail(EPIC_ERR_ARG, "t_acc must be >= 1");
   if (!efield || !gains || !images) return fail(EPIC_ERR_ARG, "efield, gains and images must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {images, "images"}, {gain_hist, "gain_hist"},
+                           {ant_status, "ant_status"}})))
+    return rc;
   const int64_t n_win = (n_samples + t_acc - 1) / t_acc;
   const int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
   RunLayout lay{};
@@ -1355,6 +1467,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   if ((rc = check_grid_supported(ap))) return rc;
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {image, "image"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
   const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
@@ -1378,6 +1491,7 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   if ((rc = check_grid_supported(ap, true))) return rc;
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   if (!efield || !gains || !dL_dI || !dL_dg) return fail(EPIC_ERR_ARG, "efield, gains, dL_dI and dL_dg must not be NULL");
+  if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {dL_dI, "dL_dI"}, {dL_dg, "dL_dg"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
   const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
@@ -1415,6 +1529,7 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
     ArrayPlan& ap = plan->arrays[i];
     if ((rc = check_grid_supported(ap))) return rc;
     if (!efield[i]) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
+    if ((rc = check_aligned({{efield[i], "efield"}}))) return rc;
     const HostArray& h = ap.h;
     std::vector<int> trs{1};
     if (epic::dft_supported(h.nx, h.na, dft_nslots(ap))) trs.push_back(2);

@@ -134,7 +134,7 @@ struct AdjointArgs {
 
 // Batched execution over several arrays (one launch per stage).
 constexpr int kMaxBatch = 16;
-enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3, kEngDftCls = 4 };   // kEngDftCls: not batched
+enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3, kEngDftCls = 4 };
 // Engine code of an array: 100 * engine + (N / 32) * 10 + (APL or R).
 inline int engine_code(int engine, int N, int param) { return 100 * engine + (N / 32) * 10 + param; }
 
@@ -197,6 +197,9 @@ hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);
 // snapshot form (a.t_acc >= 1, a.snap set; N <= 64)
 hipError_t launch_image_snap(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_grid(int N, const GridArgs& a, hipStream_t s);
+// n integer-format samples (ci4 / ci8) decoded as the imaging engines decode
+// them, to int16 (re, im) pairs
+hipError_t launch_unpack(const uint8_t* efield, int64_t n, int fmt, int16_t* out, hipStream_t s);
 hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
                          float* image, hipStream_t s);

@@ -113,6 +113,7 @@ bool batch_engine_supported(int code) {
     case 100 * kEngDft + 22: case 100 * kEngDft + 24: case 100 * kEngDft + 28:
     case 100 * kEngCls + 42: case 100 * kEngCls + 84:
     case 100 * kEngClsBig + 42: case 100 * kEngClsBig + 84:
+    case 100 * kEngDftCls + 42: case 100 * kEngDftCls + 84:   // own launches in the batched sequence
       return true;
     default:
       return false;

@@ -192,10 +192,29 @@ __global__ __launch_bounds__(256) void k_reduce(const float* partial, int splits
   image[i] = float(s * scale);
 }
 
+// ---------------------------------------------------------------------------
+// Integer E-field samples decoded by the imaging path's own unpacking
+// (load_raw_global + unpack_raw), written as int16 (re, im) pairs
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_unpack(const uint8_t* efield, int64_t n, int fmt, short2* out) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float2 v = unpack_raw(load_raw_global(efield + i * efmt_bytes(fmt), 0, fmt), fmt);
+  out[i] = make_short2(short(v.x), short(v.y));
+}
+
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_unpack(const uint8_t* efield, int64_t n, int fmt, int16_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (fmt != kCI4 && fmt != kCI8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_unpack, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, efield, n, fmt,
+                     reinterpret_cast<short2*>(out));
+  return hipGetLastError();
+}
+
 int grid_lanes(int N) { return N; }
 int grid_pitch(int N) { return N + 2; }
 

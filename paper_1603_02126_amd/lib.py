@@ -69,6 +69,10 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "epic_host_band_coordinate": (ctypes.c_int, [ctypes.POINTER(ArrayDesc), ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.c_void_p]),
+    "epical_set_denominator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "epic_plan_get_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "epic_debug_unpack": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "epic_plan_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
     "epic_plan_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "epic_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -297,6 +301,38 @@ class Plan:
         """epical_set_band: gains shared over channels b0..b1-1 (BAND_MEAN / BAND_POLY; BAND_NONE clears)."""
         _check(load().epical_set_band(self._h, int(array), int(b0), int(b1), int(mode), int(deg_amp),
                                       int(deg_phase)))
+
+    def set_denominator(self, array: int, D):
+        """epical_set_denominator: caller-supplied D [n_pix, F, Na] (or [F, Na]) complex128."""
+        d = np.ascontiguousarray(D, np.complex128)
+        _check(load().epical_set_denominator(self._h, int(array), d.ctypes.data))
+
+    def get_cells(self, array: int):
+        """epic_plan_get_cells: (ixy [Na, K, 2] int32, w [Na, K] float32) read back from the device."""
+        s = self.specs[array]
+        K = 1 if int(s.kernel) == 1 else 4
+        na = len(s.ant_xy)
+        ixy = np.zeros((na, K, 2), np.int32)
+        w = np.zeros((na, K), np.float32)
+        _check(load().epic_plan_get_cells(self._h, int(array), ixy.ctypes.data, w.ctypes.data))
+        return ixy, w
+
+    def debug_unpack(self, array: int, packed, n=None, out=None, stream=None):
+        """epic_debug_unpack: the first n samples of a packed integer stream as int16 [n, 2]."""
+        torch = _torch()
+        if not isinstance(packed, torch.Tensor) or packed.device != self.device or not packed.is_contiguous():
+            raise ValueError("packed must be a contiguous tensor on the plan's device")
+        bpe = {CI4: 1, CI8: 2, CF32: 8}[int(self.specs[array].efmt)]
+        avail = packed.numel() * packed.element_size() // bpe
+        n = avail if n is None else int(n)
+        if n < 0 or n > avail:
+            raise ValueError("n exceeds the samples held by packed")
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.int16, device=self.device)
+        po = _req(out, torch.int16, (n, 2), "out", self.device)
+        _check(load().epic_debug_unpack(self._h, int(array), ctypes.c_void_p(packed.data_ptr()), n, po,
+                                        _stream(stream)))
+        return out
 
     def set_option(self, key: int, value: int):
         _check(load().epic_plan_set_option(self._h, int(key), int(value)))

@@ -246,6 +246,41 @@ def efield_channel(wl: Workload, ch: int, dtype=np.complex128):
     return E
 
 
+def loss_target_sky(wl: Workload, n_src: int = 50):
+    """The loss target's sky of the differentiable workload: the n_src
+    brightest sources of the calibration model (data units) and the receiver
+    noise power in data units, sigma_r / quant_scale^2."""
+    order = np.argsort(-wl.model_lmS[:, 2], kind="stable")[:n_src]
+    return wl.model_lmS[order].copy(), wl.sigma_r / (wl.quant_scale * wl.quant_scale)
+
+
+def tone_efield(ant_xy, freq_hz, src_lmS, sigma: float) -> np.ndarray:
+    """A noiseless stand-in for a sky with receiver noise, as a float32
+    stream [T, F, Na, 2] with T = n_src + Na: source s radiates
+    sqrt(S_s) exp(2 pi i s t / T) and antenna a adds its own tone
+    sqrt(sigma) exp(2 pi i (n_src + a) t / T), with unit gains:
+
+        E_a(f, t) = sum_s sqrt(S_s) e^{2 pi i s t / T} exp(-2 pi i f r_a . s_s / c)
+                    + sqrt(sigma) e^{2 pi i (n_src + a) t / T}.
+
+    All T tones are distinct over the T samples, so every product of two
+    different tones averages to zero over the stream: time averages of
+    second moments equal those of the stochastic sky of the signal model."""
+    ant_xy = np.asarray(ant_xy, np.float64)
+    src = np.asarray(src_lmS, np.float64)
+    ns, na = src.shape[0], ant_xy.shape[0]
+    T = ns + na
+    t = np.arange(T, dtype=np.float64)[:, None]
+    amp_s = np.sqrt(src[:, 2])[None, :] * np.exp(2j * np.pi * np.arange(ns)[None, :] * t / T)     # [T, Ns]
+    amp_n = np.sqrt(sigma) * np.exp(2j * np.pi * (ns + np.arange(na))[None, :] * t / T)           # [T, Na]
+    out = np.empty((T, len(freq_hz), na, 2), np.float32)
+    for c, f in enumerate(np.asarray(freq_hz, np.float64)):
+        E = amp_s @ geometric_phase(ant_xy, f, src[:, :2]).T + amp_n
+        out[:, c, :, 0] = E.real
+        out[:, c, :, 1] = E.imag
+    return out
+
+
 def quantise(x: np.ndarray, scale: float, lo: int, hi: int) -> np.ndarray:
     """Round half up then clip: the digitiser's integer code for x / scale."""
     return np.clip(np.floor(x / scale + 0.5), lo, hi).astype(np.int8)

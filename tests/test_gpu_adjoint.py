@@ -102,9 +102,28 @@ def test_autograd_central_differences(cuda):
     plan.close()
 
 
+def model_image_gpu(wl, dev):
+    """The loss target of the differentiable workload: the expected image of
+    its 50 brightest model sources plus the receiver noise (data units), made
+    by the library's fixed-gain imaging of a tone sky whose time average is
+    that expectation exactly (unit gains, complex float samples)."""
+    import torch
+    from paper_1603_02126_amd import lib
+    a = wl.array
+    src, sigma = synth.loss_target_sky(wl)
+    tones = synth.tone_efield(a.ant_xy, a.freq_hz, src, sigma)
+    spec = synth.dataclasses.replace(a, efmt=synth.FMT_CF32)
+    with lib.Plan([spec]) as plan:
+        ones = torch.ones((a.n_chan, a.n_ant), dtype=torch.complex128, device=dev)
+        M = plan.image(0, torch.from_numpy(tones).to(dev), tones.shape[0], ones)
+    return M, src, sigma
+
+
 def test_adjoint_full_size_sampled_channels(cuda):
     """Differentiable workload at full size (256 antennas, 8+8-bit, 64
-    channels, 64x64, 1000 samples); the oracle checks two channels."""
+    channels, 64x64, 1000 samples), loss L = sum (I - M)^2 with M the model
+    image of 50 point sources and the noise floor; the oracle checks M and the
+    gradient on two channels."""
     import torch
     from paper_1603_02126_amd.autograd import epic_image
     wl = synth.config_diff()
@@ -114,7 +133,12 @@ def test_adjoint_full_size_sampled_channels(cuda):
     plan = lib.Plan([a])
     e = torch.from_numpy(packed).to(cuda)
     g = wl.g0
-    M = np.random.default_rng(5).uniform(0, 1, size=(a.n_chan, a.ny, a.nx))
+    Mt, src, sigma = model_image_gpu(wl, cuda)
+    M = Mt.double().cpu().numpy()
+    cells = O.grid_cells(a.ant_xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    for c in (0, 41):
+        ref_M = O.model_image(cells, a.nx, a.ny, float(a.n_ant), a.ant_xy, a.freq_hz[c], src, sigma)
+        assert np.abs(M[c] - ref_M).max() <= 1e-5 * np.abs(ref_M).max()
     gt = torch.from_numpy(g).to(cuda).requires_grad_(True)
     img = epic_image(gt, plan, 0, e, wl.n_samples)
     loss = ((img.double() - torch.from_numpy(M).to(cuda)) ** 2).sum()

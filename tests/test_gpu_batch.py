@@ -110,3 +110,37 @@ def test_autotune_then_run_matches_oracle(cuda):
         assert gain_err(g, ref["gains"][-1]) <= GAIN_RTOL, w.name
         assert image_err(img, ref["image"]).max() <= IMAGE_RTOL, w.name
     plan.close()
+
+
+def test_graph_follows_option_changes_and_new_inputs(cuda):
+    """With graph replay on, changing the time splits or the transform, or the
+    number of samples, between two calls (no synchronisation in between)
+    re-records the graph: each call matches the FP64 oracle on fresh E-field
+    contents."""
+    import torch
+    from paper_1603_02126_amd import lib
+    wls = _small_uneven(n_chan=2, n_samples=90)
+    packs = [synth.make_efield(w) for w in wls]
+    alt = [synth.make_efield(w.replace(seed=w.seed + 77)) for w in wls]
+    plan = _plan(wls, {lib.OPT_BATCH: 1, lib.OPT_GRAPH: 1})
+    es = [torch.from_numpy(p).to(cuda) for p in packs]
+    calls = [({lib.OPT_SPLITS: 3}, packs, 90), ({lib.OPT_SPLITS: 1}, alt, 90), ({lib.OPT_TRANSFORM: 2}, packs, 90),
+             ({lib.OPT_TRANSFORM: 1, lib.OPT_SPLITS: 5}, alt, 61)]
+    outs = []
+    for opts, src, T in calls:
+        for k, v in opts.items():
+            plan.set_option(k, v)
+        for e, p in zip(es, src):
+            e.copy_(torch.from_numpy(p), non_blocking=False)
+        gs = [torch.from_numpy(w.g0.copy()).to(cuda) for w in wls]
+        imgs = [torch.zeros((w.array.n_chan, w.array.ny, w.array.nx), dtype=torch.float32, device=cuda) for w in wls]
+        plan.run(es, T, gs, imgs)
+        outs.append(([g.clone() for g in gs], [i.clone() for i in imgs]))
+    torch.cuda.synchronize()
+    for (opts, src, T), (gs, imgs) in zip(calls, outs):
+        for w, p, g, img in zip(wls, src, gs, imgs):
+            w2 = w.replace(n_samples=T)
+            ref = oracle_run(w2, p[:T])
+            assert gain_err(g.cpu().numpy(), ref["gains"][-1]) <= GAIN_RTOL, (opts, w.name)
+            assert image_err(img.cpu().numpy(), ref["image"]).max() <= IMAGE_RTOL, (opts, w.name)
+    plan.close()

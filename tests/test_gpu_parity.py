@@ -121,7 +121,7 @@ def test_epical_update_matches_oracle(cuda):
         g = torch.from_numpy(g0.copy()).to(cuda)
         tp = torch.from_numpy(tap).to(cuda)
         plan.epical_update(0, e, 0, 40, tp[:40], kq, g, finalize=False)   # accumulate in two calls
-        plan.epical_update(0, e, 40, 50, tp[40:], kq, g, finalize=True)
+        plan.epical_update(0, e, 40, 50, tp[40:].clone(), kq, g, finalize=True)   # own allocation: 256-byte aligned
         got = g.cpu().numpy()
         assert float(kq.abs().max()) == 0.0
     pb = O.Problem.from_workload(wl)

@@ -780,3 +780,38 @@ def test_snapshots_average_to_the_run_image_and_tap_power():
     one = O.run_channel_snapshots(E, pb, 0, wl.g0[0], 1)
     kx, ky = O.channel_setup(pb, 0)["k0"]
     np.testing.assert_allclose(one["images"][:, ky, kx], np.abs(run["taps"]) ** 2, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# loss target of the differentiable form: the expected image of a model sky
+# ---------------------------------------------------------------------------
+
+def test_model_image_is_the_time_average_of_a_tone_sky():
+    """model_image's closed form equals the oracle's own time-averaged image
+    (grid, DFT, square, mean) of a stream in which every source and every
+    antenna's noise is a distinct tone: over the whole stream the cross terms
+    of different tones average to exactly zero."""
+    wl = synth.config_small(n=16, n_ant=20, n_chan=2, kernel=2)
+    a = wl.array
+    src = wl.model_lmS[:5]
+    sigma = 3.7
+    cells = O.grid_cells(a.ant_xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    tones = synth.tone_efield(a.ant_xy, a.freq_hz, src, sigma)
+    for f in range(a.n_chan):
+        M = O.model_image(cells, a.nx, a.ny, float(a.n_ant), a.ant_xy, a.freq_hz[f], src, sigma)
+        E = tones[:, f, :, 0].astype(np.float64) + 1j * tones[:, f, :, 1].astype(np.float64)
+        I = O.image_fixed_gains(E, np.ones(a.n_ant), cells, a.nx, a.ny, float(a.n_ant))
+        assert np.abs(M - I).max() <= 1e-6 * np.abs(M).max()
+
+
+def test_model_image_closed_forms():
+    """A single source at the phase centre, no noise: pixel 0 holds S (every
+    A_a(0) = 1); noise alone with the nearest-cell kernel: every pixel holds
+    sigma / Na (|A_a(k)| = 1)."""
+    wl = synth.config_small(n=16, n_ant=12, n_chan=1, kernel=1)
+    a = wl.array
+    cells = O.grid_cells(a.ant_xy, a.dx, a.dy, a.x0, a.y0, a.nx, a.ny, a.kernel)
+    M = O.model_image(cells, a.nx, a.ny, 12.0, a.ant_xy, a.freq_hz[0], np.array([[0.0, 0.0, 7.0]]), 0.0)
+    assert abs(M[0, 0] - 7.0) <= 1e-12
+    M = O.model_image(cells, a.nx, a.ny, 12.0, a.ant_xy, a.freq_hz[0], np.zeros((0, 3)), 5.0)
+    np.testing.assert_allclose(M, 5.0 / 12.0, rtol=1e-12)

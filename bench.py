@@ -852,6 +852,8 @@ def main():
         out = bench_diff(args, dev)
     else:
         out = bench_single(args, dev)
+    if _POOL is not None:
+        _POOL.shutdown()
     print(json.dumps(out), flush=True)
 
 

@@ -360,6 +360,28 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
              float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
              epic_stream_t stream);
 
+/* epic_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * loop, arguments, layouts and results as epic_run, with every intermediate
+ * buffer (FP32 calibration per interval, partial images, the gain history
+ * when gain_hist is NULL, the band solve's exchange area) in one static
+ * device array of EPIC_STATIC_SCRATCH_BYTES per GPU, allocated when the
+ * library's code is loaded on the device and held until the process ends.
+ * The call makes no device or host allocation: it launches the per-array
+ * kernels of epic_run (no batched work list, no graph, no timing events,
+ * whatever the plan's options say).  If the run does not fit, the time splits
+ * of the imaging launches are reduced (results agree with epic_run within
+ * rounding); if it still does not fit, EPIC_ERR_ARG (pass gain_hist, or fewer
+ * samples or channels per call).  Every call on a GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (several streams, threads or
+ * plans) race and give wrong results; calls in one stream order are safe.
+ * The array's device address is looked up once per device when a plan is
+ * created on it; if that failed, this call returns EPIC_ERR_HIP. */
+#define EPIC_STATIC_SCRATCH_BYTES (64ll << 20)
+int epic_run_noalloc(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+                     float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
+                     epic_stream_t stream);
+
 /* Snapshot images of one array: the calibrated loop of epic_run (the same
  * calibration solve and gains) with one image per window of t_acc
  * consecutive samples instead of one image over the run -- the short

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -347,6 +348,49 @@ int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int half =
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Static device scratch of the allocation-free run (epic_run_noalloc): every
+// GPU the library runs on holds one copy of this array, at its own address,
+// until the process ends.  Host code never uses the array's name as an
+// address: the address on each device comes from hipGetSymbolAddress, taken
+// once per device (with that device current) when a plan is created there.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(EPIC_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+bool g_static_done[kMaxDevices];
+hipError_t g_static_err[kMaxDevices];
+void* g_static_ptr[kMaxDevices];
+
+// The device address of `scratch` on device `dev` (the current device).
+hipError_t static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_done[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_static_err[dev] = e;
+    g_static_ptr[dev] = e == hipSuccess ? ptr : nullptr;
+    g_static_done[dev] = true;
+  }
+  return g_static_err[dev];
+}
+
+// The address taken at set-up, or null with the set-up error.
+void* static_scratch_ptr(int dev, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (dev < 0 || dev >= kMaxDevices || !g_static_done[dev]) {
+    *err = hipErrorNotInitialized;
+    return nullptr;
+  }
+  *err = g_static_err[dev];
+  return g_static_ptr[dev];
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
 struct ArrayPlan {
@@ -450,7 +494,7 @@ int upload(T** dst, const T* src, size_t n) {
   return EPIC_OK;
 }
 
-int scratch(epic_plan_t p, size_t bytes, void** out) {
+int plan_scratch(epic_plan_t p, size_t bytes, void** out) {
   if (bytes > p->scratch_bytes) {
     if (p->d_scratch) {
       hipError_t e = hipDeviceSynchronize();
@@ -668,6 +712,9 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
+  // the allocation-free run's scratch address on this device (its error, if
+  // any, is reported by epic_run_noalloc)
+  static_scratch_setup(p->device);
   p->arrays.resize(n_arrays);
   for (int i = 0; i < n_arrays; ++i) {
     ArrayPlan& ap = p->arrays[i];
@@ -1307,16 +1354,20 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
   return EPIC_OK;
 }
 
-int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
-             float* const* image, double* const* gain_hist, uint32_t* const* ant_status, epic_stream_t stream) {
+// Argument checks of a run over every array of the plan and its scratch
+// layout (splits[i] > 0 overrides the time splits of array i).
+static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+                       float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
+                       std::vector<RunLayout>& lay, size_t& need, bool& all_batchable, bool& any_band,
+                       const std::vector<int>* splits = nullptr) {
   if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image arrays must not be NULL");
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
   const int na_arr = int(plan->arrays.size());
-  std::vector<RunLayout> lay(na_arr);
-  size_t need = 0;
-  bool all_batchable = na_arr <= epic::kMaxBatch;
-  bool any_band = false;
+  lay.assign(na_arr, RunLayout{});
+  need = 0;
+  all_batchable = na_arr <= epic::kMaxBatch;
+  any_band = false;
   for (int i = 0; i < na_arr; ++i) {
     int rc = check_plan(plan, i);
     if (rc) return rc;
@@ -1330,18 +1381,31 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
                              {gain_hist ? gain_hist[i] : nullptr, "gain_hist"},
                              {ant_status ? ant_status[i] : nullptr, "ant_status"}})))
       return rc;
-    rc = layout_array(ap, n_samples, pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits),
-                      size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
+    const int sp = splits && (*splits)[i] > 0 ? (*splits)[i]
+                                                : pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
+    rc = layout_array(ap, n_samples, sp, size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
     all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
+  return EPIC_OK;
+}
+
+int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+             float* const* image, double* const* gain_hist, uint32_t* const* ant_status, epic_stream_t stream) {
+  std::vector<RunLayout> lay;
+  size_t need = 0;
+  bool all_batchable = false, any_band = false;
+  int rc = prepare_run(plan, efield, n_samples, gains, image, gain_hist, ant_status, lay, need, all_batchable,
+                       any_band);
+  if (rc) return rc;
+  const int na_arr = int(plan->arrays.size());
   if (any_band && plan->batch == 1)
     return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band run in the per-array form (EPIC_OPT_BATCH 0 or 2)");
   const bool batched = !any_band && all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));
   if (plan->graph && !batched)
     return fail(EPIC_ERR_UNSUPPORTED, "graph replay needs the batched form (EPIC_OPT_BATCH and supported engines)");
   void* scr = nullptr;
-  int rc = scratch(plan, need, &scr);
+  rc = plan_scratch(plan, need, &scr);
   if (rc) return rc;
   if (batched) {
     if (!plan->d_counter) {
@@ -1411,6 +1475,48 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "graph stream ordering");
 }
 
+int epic_run_noalloc(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
+                     float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
+                     epic_stream_t stream) {
+  std::vector<RunLayout> lay;
+  size_t need = 0;
+  bool all_batchable = false, any_band = false;
+  int rc = prepare_run(plan, efield, n_samples, gains, image, gain_hist, ant_status, lay, need, all_batchable,
+                       any_band);
+  if (rc) return rc;
+  // fewer time splits (smaller partial images) until the run fits the static
+  // scratch: halve the splits of the array whose partials take the most room
+  std::vector<int> sp(lay.size());
+  for (size_t i = 0; i < lay.size(); ++i) sp[i] = lay[i].splits;
+  while (need > kStaticScratchBytes) {
+    int best = -1;
+    size_t best_bytes = 0;
+    for (size_t i = 0; i < lay.size(); ++i) {
+      const HostArray& h = plan->arrays[i].h;
+      const size_t b = size_t(sp[i]) * h.F * h.nx * h.ny * sizeof(float);
+      if (sp[i] > 1 && b > best_bytes) {
+        best = int(i);
+        best_bytes = b;
+      }
+    }
+    if (best < 0)
+      return fail(EPIC_ERR_ARG, "the run needs %zu bytes of scratch; the static scratch of epic_run_noalloc holds "
+                  "%zu (pass gain_hist, or fewer samples or channels per call)", need, kStaticScratchBytes);
+    sp[best] = (sp[best] + 1) / 2;
+    if ((rc = prepare_run(plan, efield, n_samples, gains, image, gain_hist, ant_status, lay, need, all_batchable,
+                          any_band, &sp)))
+      return rc;
+  }
+  hipError_t e = hipSuccess;
+  char* scr = static_cast<char*>(static_scratch_ptr(plan->device, &e));
+  if (!scr) return hip_fail(e, "static scratch address (hipGetSymbolAddress at plan creation)");
+  // per-array launches only (no work list, graph or timing events); every
+  // buffer in the scratch is written before it is read, the band solve's
+  // barrier flags by a fill kernel
+  return enqueue_run(plan, lay, scr, efield, n_samples, gains, image, gain_hist, ant_status,
+                     static_cast<hipStream_t>(stream), false, false);
+}
+
 int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int64_t n_samples, int64_t t_acc,
                        double* gains, float* images, double* gain_hist, uint32_t* ant_status, epic_stream_t stream) {
   int rc = check_plan(plan, array);
@@ -1434,7 +1540,7 @@ int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int6
   bool any_band = false;
   if ((rc = layout_array(ap, n_samples, splits, 0, lay, need, any_band))) return rc;
   void* scr = nullptr;
-  if ((rc = scratch(plan, need, &scr))) return rc;
+  if ((rc = plan_scratch(plan, need, &scr))) return rc;
   char* sc = static_cast<char*>(scr);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const HostArray& h = ap.h;
@@ -1473,7 +1579,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
-  rc = scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
+  rc = plan_scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float2* u = static_cast<float2*>(scr);
@@ -1497,7 +1603,7 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
-  rc = scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);
+  rc = plan_scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   float2* u = static_cast<float2*>(scr);
@@ -1543,7 +1649,7 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
     const size_t ub = align256(size_t(h.F) * h.na * sizeof(float2));
     const size_t ib = align256(size_t(h.F) * h.nx * h.ny * sizeof(float));
     void* scr = nullptr;
-    if ((rc = scratch(plan, ub + ib + size_t(max_sp) * h.F * h.nx * h.ny * sizeof(float), &scr))) return rc;
+    if ((rc = plan_scratch(plan, ub + ib + size_t(max_sp) * h.F * h.nx * h.ny * sizeof(float), &scr))) return rc;
     char* base_p = static_cast<char*>(scr);
     std::vector<float2> ones(size_t(h.F) * h.na, make_float2(1.f, 0.f));
     hipError_t e = hipMemcpy(base_p, ones.data(), ones.size() * sizeof(float2), hipMemcpyHostToDevice);

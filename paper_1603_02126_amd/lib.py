@@ -84,6 +84,8 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "epic_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_run_snapshots": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
@@ -415,7 +417,11 @@ class Plan:
                                     _stream(stream)))
 
     # -- fused loop
-    def run(self, efields, n_samples, gains, images, gain_hist=None, status=None, stream=None):
+    def run_noalloc(self, efields, n_samples, gains, images, gain_hist=None, status=None, stream=None):
+        """epic_run_noalloc: epic_run with every intermediate in the library's static device scratch."""
+        self.run(efields, n_samples, gains, images, gain_hist, status, stream, _entry="epic_run_noalloc")
+
+    def run(self, efields, n_samples, gains, images, gain_hist=None, status=None, stream=None, _entry="epic_run"):
         """epic_run over all arrays; lists of tensors, one per array."""
         torch = _torch()
         n = len(self.specs)
@@ -444,7 +450,7 @@ class Plan:
         a_h = VP(*ph) if gain_hist is not None else None
         a_s = VP(*ps) if status is not None else None
         keep += [a_e, a_g, a_i, a_h, a_s]
-        _check(load().epic_run(self._h, a_e, int(n_samples), a_g, a_i, a_h, a_s, _stream(stream)))
+        _check(getattr(load(), _entry)(self._h, a_e, int(n_samples), a_g, a_i, a_h, a_s, _stream(stream)))
 
     def run_snapshots(self, i, efield, n_samples, t_acc, gains, images, gain_hist=None, status=None, stream=None):
         """epic_run_snapshots: images [ceil(n_samples / t_acc), F, ny, nx] float32, one per window."""

@@ -345,6 +345,65 @@ int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int half =
   return int(S);
 }
 
+// Multi-class schedule of the dense residue-class engine (N = 64 R): the
+// sub-cells q = j mod 64 of sub-cell columns [32 half, 32 half + 32) are
+// balanced over `owners` lanes (all waves of a frame); a lane's slots of one
+// sub-cell are consecutive, the first marked first, the last marked last.
+// Padding slots: weight 0, first, not last.
+int build_slots_dense(const HostArray& h, int owners, int half, std::vector<uint32_t>& table) {
+  std::vector<int32_t> ix, iy;
+  std::vector<double> w;
+  grid_cells(h, ix, iy, w);
+  struct Contrib { int a, jx, jy; float w; };
+  std::vector<std::vector<Contrib>> sub(64 * 64);
+  for (int a = 0; a < h.na; ++a) {
+    if (h.flag[a]) continue;
+    for (int k = 0; k < h.k2; ++k) {
+      const size_t q = size_t(a) * h.k2 + k;
+      if (w[q] == 0.0 || (ix[q] % 64) / 32 != half) continue;
+      sub[size_t(iy[q] % 64) * 64 + ix[q] % 64].push_back({a, ix[q], iy[q], float(w[q])});
+    }
+  }
+  std::vector<int> order;
+  for (int c = 0; c < 64 * 64; ++c)
+    if (!sub[c].empty()) order.push_back(c);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sub[x].size() > sub[y].size(); });
+  std::vector<std::vector<int>> lane_cells(owners);
+  std::vector<size_t> load(owners, 0);
+  for (int c : order) {
+    int best = 0;
+    for (int l = 1; l < owners; ++l)
+      if (load[l] < load[best]) best = l;
+    lane_cells[best].push_back(c);
+    load[best] += sub[c].size();
+  }
+  size_t S = 0;
+  for (int l = 0; l < owners; ++l) S = std::max(S, load[l]);
+  table.assign(2 * S * owners, 0u);
+  for (int l = 0; l < owners; ++l) {
+    size_t s = 0;
+    for (int c : lane_cells[l]) {
+      const auto& lst = sub[c];
+      for (size_t i = 0; i < lst.size(); ++i, ++s) {
+        const Contrib& q = lst[i];
+        uint32_t code = uint32_t(q.a) | uint32_t(q.jx % 64) << 12 | uint32_t(q.jy % 64) << 18 |
+                        uint32_t(q.jx / 64) << 24 | uint32_t(q.jy / 64) << 26;
+        if (i == 0) code |= 1u << 31;
+        if (i + 1 == lst.size()) code |= 1u << 30;
+        uint32_t wb;
+        std::memcpy(&wb, &q.w, 4);
+        table[2 * (s * owners + l)] = code;
+        table[2 * (s * owners + l) + 1] = wb;
+      }
+    }
+    for (; s < S; ++s) {
+      table[2 * (s * owners + l)] = 1u << 31;
+      table[2 * (s * owners + l) + 1] = 0u;
+    }
+  }
+  return int(S);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -403,6 +462,8 @@ struct ArrayPlan {
   int n_slots_dft = 0;
   uint2* d_slots_h = nullptr;     // 64 x 64: half-frame schedule (two halves of rows)
   int n_slots_h0 = 0, n_slots_h1 = 0;
+  uint2* d_slots_m = nullptr;     // 128 / 256, integer formats: multi-class schedules (two halves)
+  int n_slots_m0 = 0, n_slots_m1 = 0;
   uint8_t* d_flag = nullptr;
   // tuning (0 = plan default): transform 1 FFT / 2 DFT-GEMM, time splits
   int tune_transform = 0;
@@ -474,6 +535,7 @@ void free_array(ArrayPlan& p) {
   hipFree(p.d_slots);
   hipFree(p.d_slots_dft);
   hipFree(p.d_slots_h);
+  hipFree(p.d_slots_m);
   hipFree(p.d_flag);
   hipFree(p.d_k0);
   hipFree(p.d_A);
@@ -577,19 +639,39 @@ struct Timed {
   }
 };
 
-// Workgroups of one time split per channel (class groups of the N = 256 engine).
-int units_for(int N) { return N == 256 ? 4 : 1; }
+// The dense residue-class engine's schedules in an array's imaging arguments.
+void with_dense_slots(ImageArgs& ia, const ArrayPlan& ap) {
+  ia.slots_m = ap.d_slots_m;
+  ia.n_slots_m0 = ap.n_slots_m0;
+  ia.n_slots_m1 = ap.n_slots_m1;
+}
+
+// The fields of an array's imaging arguments that decide which engine runs it.
+ImageArgs engine_probe(const ArrayPlan& ap) {
+  ImageArgs ia{};
+  ia.Na = ap.h.na;
+  ia.fmt = ap.h.efmt;
+  ia.slots_h = ap.d_slots_h;
+  ia.n_slots_h0 = ap.n_slots_h0;
+  ia.n_slots_h1 = ap.n_slots_h1;
+  with_dense_slots(ia, ap);
+  return ia;
+}
+
+// Workgroups of one time split per channel (class groups of the N = 256 engines).
+int units_for(const ArrayPlan& ap) { return epic::cls_groups(engine_probe(ap), ap.h.nx); }
 // Frames a workgroup images at once.
 int slots_for(int N) { return N >= 128 ? 1 : 4 * (64 / N); }
 
-int pick_splits(epic_plan_t p, int F, int64_t T, int N, int tuned = 0) {
+int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0) {
+  const int F = ap.h.F, N = ap.h.nx;
   if (tuned > 0) return int(std::max<int64_t>(1, std::min<int64_t>(tuned, std::max<int64_t>(1, T))));
   if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
   // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames
   // per slot; at 64 x 64 (the two-waves-per-SIMD engines: eight waves) >= 16
   // frames per wave, which repays a workgroup's set-up and reduction (the
   // 1000-sample differentiable workload: 31 splits 1.20 ms, 8 splits 1.08 ms)
-  const int64_t units = int64_t(F) * units_for(N);
+  const int64_t units = int64_t(F) * units_for(ap);
   int64_t s = (2048 + units - 1) / units;
   const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
   s = std::min<int64_t>(s, std::max<int64_t>(1, T / per_split));
@@ -761,6 +843,14 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
         ap.n_slots_h1 = build_slots_cls(ap.h, hi, 1);
         tab.insert(tab.end(), hi.begin(), hi.end());
         rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      }
+      if (!rc && ap.h.efmt != EPIC_CF32) {
+        std::vector<uint32_t> hi;
+        const int owners = 64 * (ap.h.nx == 256 ? 8 : 4);   // the lanes of a frame's waves
+        ap.n_slots_m0 = build_slots_dense(ap.h, owners, 0, tab);
+        ap.n_slots_m1 = build_slots_dense(ap.h, owners, 1, hi);
+        tab.insert(tab.end(), hi.begin(), hi.end());
+        rc = upload(&ap.d_slots_m, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }
     }
     if (rc) {
@@ -1065,6 +1155,7 @@ static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
                dft ? dft_slots(ap) : ap.d_slots, dft ? dft_nslots(ap) : ap.n_slots, splits, partial,
                ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
+  with_dense_slots(ia, ap);
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     hipError_t e = dft ? epic::launch_image_dft(N, ia, s) : epic::launch_image(N, ia, s);
@@ -1116,12 +1207,7 @@ static int solve_ps(const HostArray& h) {
 // which the persistent kernel's body does not (there it measured slower).
 static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
   const int code = engine_of(plan, ap), N = ap.h.nx;
-  ImageArgs ia{};
-  ia.Na = ap.h.na;
-  ia.fmt = ap.h.efmt;
-  ia.slots_h = ap.d_slots_h;
-  ia.n_slots_h0 = ap.n_slots_h0;
-  ia.n_slots_h1 = ap.n_slots_h1;
+  const ImageArgs ia = engine_probe(ap);
   if (code / 100 == epic::kEngFft) return epic::pair_engine(ia, N);
   if (code / 100 == epic::kEngCls) return epic::cls_pair_engine(ia, N);
   if (code / 100 == epic::kEngClsBig || code / 100 == epic::kEngDftCls) return true;
@@ -1309,6 +1395,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
                    reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal, ap.d_slots, ap.n_slots,
                    lay[i].splits, reinterpret_cast<float*>(scr + lay[i].p_off), ap.d_slots_h, ap.n_slots_h0,
                    ap.n_slots_h1};
+      with_dense_slots(ia, ap);
       hipError_t e = dft ? epic::launch_image_dft(h.nx, ia, s) : epic::launch_image(h.nx, ia, s);
       if (e != hipSuccess) return hip_fail(e, "imaging launch");
     }
@@ -1382,7 +1469,7 @@ static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_sa
                              {ant_status ? ant_status[i] : nullptr, "ant_status"}})))
       return rc;
     const int sp = splits && (*splits)[i] > 0 ? (*splits)[i]
-                                                : pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
+                                                : pick_splits(plan, ap, n_samples, ap.tune_splits);
     rc = layout_array(ap, n_samples, sp, size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
     all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
@@ -1534,7 +1621,7 @@ int epic_run_snapshots(epic_plan_t plan, int32_t array, const void* efield, int6
                            {ant_status, "ant_status"}})))
     return rc;
   const int64_t n_win = (n_samples + t_acc - 1) / t_acc;
-  const int splits = pick_splits(plan, ap.h.F, n_samples, ap.h.nx, ap.tune_splits);
+  const int splits = pick_splits(plan, ap, n_samples, ap.tune_splits);
   RunLayout lay{};
   size_t need = 0;
   bool any_band = false;
@@ -1576,7 +1663,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {image, "image"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
+  const int splits = pick_splits(plan, ap, n_samples, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = plan_scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);
@@ -1600,7 +1687,7 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {dL_dI, "dL_dI"}, {dL_dg, "dL_dg"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, h.F, n_samples, h.nx, ap.tune_splits);
+  const int splits = pick_splits(plan, ap, n_samples, ap.tune_splits);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = plan_scratch(plan, ub + size_t(splits) * h.F * h.na * sizeof(double2), &scr);
@@ -1639,7 +1726,7 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
     const HostArray& h = ap.h;
     std::vector<int> trs{1};
     if (epic::dft_supported(h.nx, h.na, dft_nslots(ap))) trs.push_back(2);
-    const int base = pick_splits(plan, h.F, n_samples, h.nx, 0);
+    const int base = pick_splits(plan, ap, n_samples, 0);
     std::vector<int> sps;
     for (int c : {base / 2, base, 2 * base, 4 * base}) {
       const int v = int(std::max<int64_t>(1, std::min<int64_t>(c, n_samples)));

@@ -38,6 +38,11 @@ struct ImageArgs {
   int64_t t_acc = 0;
   float* snap = nullptr;
   double snap_scale = 0.0;
+  // multi-class schedules of the dense residue-class engine (N = 128, 256):
+  // per half of the sub-cell columns, rows of 64 x (classes per frame) sub-cell
+  // owners; null when not built
+  const uint2* slots_m = nullptr;
+  int n_slots_m0 = 0, n_slots_m1 = 0;
 };
 
 // Stage-wise gridding to HBM.
@@ -189,6 +194,10 @@ int cls_table_slots();
 bool image_supported(int N, int na, int n_slots);
 bool pair_engine(const ImageArgs& a, int N);   // the 64 x 64 two-waves-per-SIMD engine applies
 bool cls_pair_engine(const ImageArgs& a, int N);   // the 128 / 256 two-waves-per-SIMD class engine applies
+bool cls_dense_engine(const ImageArgs& a, int N);  // the dense two-waves-per-SIMD class engine applies
+// Imaging workgroups per (channel, time split) of launch_image at N = 128, 256
+// (class groups); 1 below.
+int cls_groups(const ImageArgs& a, int N);
 // Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64; its gridding
 // schedule has 64 lanes and transposed (G^T) cell offsets.
 bool dft_supported(int N, int na, int n_slots);

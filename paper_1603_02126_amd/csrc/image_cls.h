@@ -338,4 +338,213 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Residue-class engine with two waves per SIMD for dense arrays (integer
+// E-fields; 513..2048 antennas at 256 x 256, up to 1024 at 128 x 128).
+//
+// Eight waves, one class each: at R = 4 the eight classes (cy = 2 cg + j,
+// j = 0, 1; cx = 0..3) of one frame, at R = 2 the four classes of two frames
+// (samples t, t + 1).  The gridding serves all classes of a frame at once:
+// the frame's sub-cells are owned by the lanes of all its waves (a host
+// schedule per half of the sub-cell columns), and every contribution
+// z = w E'_a to sub-cell q = j mod 64 is added, for each class c, as
+//   z exp(+2 pi i jy cy / N) exp(+2 pi i jx cx / N)
+// into the owner's register sums, which go to the classes' half frames when
+// the sub-cell's last contribution has been added.  One table entry, one E'
+// and five twiddles serve eight classes (R = 4), against one table entry, one
+// E' and one twiddle per contribution and class when each wave grids its own
+// class.  Each wave then takes its class's half rows, runs the row FFTs,
+// transposes in registers and runs the column FFTs, as the paired engines do.
+// The E' of a frame (up to 2048 complex values) and the eight half frames
+// fill the LDS, so the schedules are read from memory (the same rows for
+// every workgroup of the array: cache resident), each batch of entries
+// requested while the previous one is gridded.  Workgroup barriers order the
+// staging, the two gridding passes and the row loads.
+// Multi-class slot code: antenna | qx << 12 | qy << 18 | px << 24 | py << 26
+//                        | last << 30 | first << 31
+// (padding slots: weight 0, first and not last, never stored).
+// ---------------------------------------------------------------------------
+constexpr int kClsDenseThreads = 512;
+constexpr int kClsDenseGridBatch = 2;
+
+template <int R>
+struct ClsDenseSmem {
+  static constexpr int N = 64 * R;
+  static constexpr int CPW = R == 4 ? 8 : 4;            // classes per frame (= per workgroup)
+  static constexpr int NF = 8 / CPW;                     // frames per step
+  static constexpr int NCY = CPW / R;                    // cy values per workgroup
+  static constexpr int OWNERS = 64 * CPW;                // lanes owning a frame's sub-cells
+  static constexpr int MAXA = R == 4 ? 2048 : 1024;      // E' per frame
+  static constexpr int HALF = 64 * kHalfPitch;           // float2 per wave
+  static constexpr int E_OFF = 8 * HALF * 8;             // bytes
+  static constexpr int TW_OFF = E_OFF + NF * MAXA * 8;
+  static constexpr int BYTES = TW_OFF + N * 8;
+  static_assert(BYTES <= kLdsBytes, "half frames, E' staging and twiddles fit the LDS");
+  static_assert(HALF >= kXposeFloat2, "the transpose staging reuses the half frame");
+  static_assert(4 * 64 * 64 * 4 <= E_OFF, "the class reduction reuses the half frames");
+};
+
+// Grid sub-cell columns [32 hf, 32 hf + 32) of all classes of a frame: the
+// owner's slots from `tab` (S rows of OWNERS entries, this owner's column),
+// B per batch, the next batch requested before the current one is gridded.
+// Class (cy0 + jc, cx) goes to the half frame H0 + (jc R + cx) * HALF.
+template <int R, int B>
+__device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, const float2* tw, const uint2* tab,
+                                                int S, int hf, int cy0, int owner) {
+  using L = ClsDenseSmem<R>;
+  constexpr int N = 64 * R, NCY = L::NCY, OW = L::OWNERS;
+  if (S <= 0) return;
+  float2 acc[NCY][R];
+  static_for<0, NCY>([&](auto jc) {
+    static_for<0, R>([&](auto mc) { acc[decltype(jc)::value][decltype(mc)::value] = make_float2(0.f, 0.f); });
+  });
+  uint2 nxt[B];
+  static_for<0, B>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    nxt[k] = gload(tab + (k < S ? k : S - 1) * OW + owner);
+  });
+  for (int s0 = 0; s0 < S; s0 += B) {
+    uint2 e[B];
+    static_for<0, B>([&](auto kc) { e[decltype(kc)::value] = nxt[decltype(kc)::value]; });
+    if (s0 + B < S) {
+      static_for<0, B>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        nxt[k] = gload(tab + (s0 + B + k < S ? s0 + B + k : S - 1) * OW + owner);
+      });
+    }
+    static_for<0, B>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const uint32_t code = e[k].x;
+      const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
+      const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
+      const float2 ev = epr[code & kSlotAntMask];
+      float2 tx[R], ty[NCY];
+      static_for<1, R>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        tx[m] = tw[(jx * m) & (N - 1)];
+      });
+      static_for<0, NCY>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        ty[j] = tw[(jy * (cy0 + j)) & (N - 1)];
+      });
+      const float w = __uint_as_float(e[k].y);
+      const float2 z = make_float2(w * ev.x, w * ev.y);
+      const bool first = int(code) < 0, last = (code >> 30) & 1;
+      static_for<0, NCY>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const float2 zy = cmul(z, ty[j]);
+        static_for<0, R>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          float2 c;
+          if constexpr (m == 0) c = zy;
+          else c = cmul(zy, tx[m]);
+          acc[j][m].x = first ? c.x : acc[j][m].x + c.x;
+          acc[j][m].y = first ? c.y : acc[j][m].y + c.y;
+        });
+      });
+      if (last && s0 + k < S) {
+        const int off = qy * kHalfPitch + qx - 32 * hf;
+        static_for<0, NCY>([&](auto jc) {
+          static_for<0, R>([&](auto mc) {
+            constexpr int j = decltype(jc)::value, m = decltype(mc)::value;
+            H0[(j * R + m) * L::HALF + off] = acc[j][m];
+          });
+        });
+      }
+    });
+  }
+}
+
+template <int R, int FMT>
+__device__ __forceinline__ void image_cls_dense_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
+  static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
+  using L = ClsDenseSmem<R>;
+  constexpr int N = 64 * R, NF = L::NF, CPW = L::CPW, OW = L::OWNERS;
+  constexpr int APT = L::MAXA / OW;                 // antennas per staging thread
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int tid = threadIdx.x, lam = tid & 63, wave = tid >> 6;
+  const int fs = wave / CPW, ci = wave % CPW;       // frame slot, class within the frame
+  const int cx = ci % R, cy = cg * L::NCY + ci / R, cy0 = cg * L::NCY;
+  const int owner = tid % OW;                       // sub-cell owner (and staging thread) of the frame
+  float2* H = lds + wave * L::HALF;
+  float2* H0 = lds + fs * CPW * L::HALF;            // the frame's first class buffer
+  float2* epr = reinterpret_cast<float2*>(smem + L::E_OFF) + fs * L::MAXA;
+  float2* tw = reinterpret_cast<float2*>(smem + L::TW_OFF);
+  const int S0 = a.n_slots_m0, S1 = a.n_slots_m1;
+  const int64_t tb = a.n_t * s / a.splits, te = a.n_t * (s + 1) / a.splits;
+  constexpr int bpe = FMT == kCI4 ? 1 : 2;
+
+  for (int k = tid; k < N; k += kClsDenseThreads) {
+    double sn, cs;
+    sincospi(2.0 * double(k) / double(N), &sn, &cs);
+    tw[k] = make_float2(float(cs), float(sn));
+  }
+  clear_half_row(H, lam);
+
+  float acc[64];
+  static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] = 0.f; });
+  float2 v[64];
+  uint32_t raw[APT];
+  auto fetch_raw = [&](int64_t t) {
+    const uint8_t* row = a.efield + (t * a.F + f) * int64_t(a.Na) * bpe;
+    static_for<0, APT>([&](auto ic) {
+      const int an = owner + OW * decltype(ic)::value;
+      raw[decltype(ic)::value] = (t < te && an < a.Na) ? load_raw_global(row, an, FMT).x : 0u;
+    });
+  };
+  const int64_t iters = (te - tb + NF - 1) / NF;
+  fetch_raw(tb + fs);
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t t = tb + NF * it + fs;
+    const float2* urow = a.u + (((t < te ? t : tb) / a.t_cal) * a.F + f) * int64_t(a.Na);
+    float2 uu[APT];
+    static_for<0, APT>([&](auto ic) {
+      const int an = owner + OW * decltype(ic)::value;
+      uu[decltype(ic)::value] = gload(urow + (an < a.Na ? an : a.Na - 1));
+    });
+    static_for<0, APT>([&](auto ic) {
+      const int an = owner + OW * decltype(ic)::value;
+      if (an < a.Na) epr[an] = t < te ? cmul(unpack_raw(Raw{raw[decltype(ic)::value], 0u}, FMT),
+                                             uu[decltype(ic)::value])
+                                      : make_float2(0.f, 0.f);
+    });
+    __syncthreads();                 // E' staged (and every half frame clear)
+    grid_dense_half<R, kClsDenseGridBatch>(H0, epr, tw, a.slots_m, S0, 0, cy0, owner);
+    __syncthreads();                 // every class's first half gridded
+    take_half_row<0>(v, H, lam);
+    __syncthreads();                 // every half frame read and cleared
+    grid_dense_half<R, kClsDenseGridBatch>(H0, epr, tw, a.slots_m + S0 * OW, S1, 1, cy0, owner);
+    __syncthreads();                 // second halves gridded; E' free for the next step
+    take_half_row<32>(v, H, lam);
+    fft_reg<64, +1>(v);
+    transpose64(v, H, lam);
+    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
+    fft_reg<64, +1>(v);
+    fetch_raw(t + NF);
+    static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+  }
+  // class pixels (R y + cy, R kx + cx), kx = lam; at R = 2 the two frame
+  // slots of each class are summed first
+  float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
+  if constexpr (NF == 1) {
+    static_for<0, 64>([&](auto yc) {
+      constexpr int y = decltype(yc)::value;
+      gstore(out + (R * y + cy) * N + R * lam + cx, acc[y]);
+    });
+  } else {
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(lds);
+    if (fs == 1)
+      static_for<0, 64>([&](auto yc) { red[(ci * 64 + decltype(yc)::value) * 64 + lam] = acc[decltype(yc)::value]; });
+    __syncthreads();
+    if (fs == 0) {
+      static_for<0, 64>([&](auto yc) {
+        constexpr int y = decltype(yc)::value;
+        gstore(out + (R * y + cy) * N + R * lam + cx, acc[y] + red[(ci * 64 + y) * 64 + lam]);
+      });
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace epic

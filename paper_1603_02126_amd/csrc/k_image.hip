@@ -82,6 +82,14 @@ __global__ __launch_bounds__(kClsPairThreads) void k_image_cls_pair(ImageArgs a)
   image_cls_pair_item<R, FMT, DB>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
+template <int R, int FMT>
+__global__ __launch_bounds__(kClsDenseThreads) void k_image_cls_dense(ImageArgs a) {
+  __shared__ __align__(16) uint8_t smem[ClsDenseSmem<R>::BYTES];
+  constexpr int CG = (R * R) / ClsDenseSmem<R>::CPW;
+  const int rest = blockIdx.x / a.F;
+  image_cls_dense_item<R, FMT>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_image_cls_big(ImageArgs a) {
   __shared__ __align__(16) uint8_t smem[ClsSmem<R, true>::BYTES];
@@ -271,10 +279,31 @@ bool cls_pair_engine(const ImageArgs& a, int N) {
   return a.n_slots_h0 + a.n_slots_h1 <= cap;
 }
 
+// The dense residue-class engine with two waves per SIMD: integer E-fields,
+// arrays the class-pair engine does not take, up to 2048 antennas at
+// 256 x 256 and 1024 at 128 x 128 (its E' staging of one or two frames).
+bool cls_dense_engine(const ImageArgs& a, int N) {
+  if (!(N == 128 || N == 256) || a.fmt == kCF32 || !a.slots_m || cls_pair_engine(a, N)) return false;
+  return a.Na <= (N == 256 ? ClsDenseSmem<4>::MAXA : ClsDenseSmem<2>::MAXA);
+}
+
+int cls_groups(const ImageArgs& a, int N) {
+  if (N == 256) return cls_dense_engine(a, N) ? 16 / ClsDenseSmem<4>::CPW : 4;
+  return 1;
+}
+
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
   if (N == 128 || N == 256) {
     const bool big = cls_variant(a.Na, a.n_slots) == 2;
-    const dim3 grid(a.F * (N == 256 ? 4 : 1) * a.splits);
+    const dim3 grid(a.F * cls_groups(a, N) * a.splits);
+    if (cls_dense_engine(a, N)) {
+      const dim3 blk(kClsDenseThreads);
+      if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<2, kCI4>), grid, blk, 0, s, a);
+      else if (N == 128) hipLaunchKernelGGL((k_image_cls_dense<2, kCI8>), grid, blk, 0, s, a);
+      else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<4, kCI4>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_image_cls_dense<4, kCI8>), grid, blk, 0, s, a);
+      return hipGetLastError();
+    }
     if (cls_pair_engine(a, N)) {
       const dim3 blk(kClsPairThreads);
       if (cls_pair_db(a, N)) {

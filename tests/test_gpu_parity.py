@@ -181,6 +181,24 @@ def test_run_maximum_antennas(cuda, n, efmt, kernel, na, n_samples, t_cal):
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
 
 
+@pytest.mark.parametrize("n,efmt,na,n_samples,t_cal", [
+    (256, synth.FMT_CI8, 513, 37, 10),       # just past the class-pair engine
+    (256, synth.FMT_CI4, 1500, 29, 8),
+    (128, synth.FMT_CI8, 1000, 41, 20),      # two frames per step, odd sample count
+    (128, synth.FMT_CI4, 700, 8, 3),
+])
+def test_dense_class_engine(cuda, n, efmt, na, n_samples, t_cal):
+    """The dense residue-class engine with two waves per SIMD (513..2048
+    antennas at 256 x 256, up to 1024 at 128 x 128; slot tables read from
+    memory in batches)."""
+    wl = synth.config_small(n=n, efmt=efmt, kernel=2, n_ant=na, n_chan=2, n_samples=n_samples, t_cal=t_cal)
+    packed = synth.make_efield(wl)
+    ref = oracle_run(wl, packed)
+    got = gpu_run(wl, packed, cuda)
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
 def test_dense_64_grid_with_2x2_kernel_is_an_error(cuda):
     """512 antennas with the 2 x 2 kernel give a 64 x 64 gridding schedule
     longer than the LDS slot table: a clean EPIC_ERR_UNSUPPORTED."""

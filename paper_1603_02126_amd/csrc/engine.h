@@ -112,12 +112,12 @@ __device__ __forceinline__ float2 shfl_xor2(float2 v, int m) {
   return make_float2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
 }
 
-template <int N>
+template <int N, int W = 4>
 struct Geo {
   static constexpr int PITCH = N + 2;       // complex values per LDS row
   static constexpr int FPW = 64 / N;        // frames per wave
   static constexpr int FRAME = N * PITCH;   // float2 per frame buffer
-  static constexpr int SLOTS = 4 * FPW;     // frames in flight per workgroup
+  static constexpr int SLOTS = W * FPW;     // frames in flight per workgroup of W waves
   static constexpr int LDS = SLOTS * FRAME; // float2 per workgroup
 };
 
@@ -342,10 +342,10 @@ struct DegridTable {
 //   APL: antennas per lane of the E' staging (Na <= APL * N)
 // LDS budget per workgroup: frame buffers, E' staging, then the slot table.
 // ---------------------------------------------------------------------------
-template <int N, int APL>
+template <int N, int APL, int W = 4>
 struct Budget {
-  static constexpr int FRAMES = Geo<N>::LDS * 8;
-  static constexpr int STAGE = Geo<N>::SLOTS * APL * N * 8;
+  static constexpr int FRAMES = Geo<N, W>::LDS * 8;
+  static constexpr int STAGE = Geo<N, W>::SLOTS * APL * N * 8;
   static constexpr int TAB_SLOTS = (kLdsBytes - FRAMES - STAGE) / (N * 8);   // slot rows that fit
 };
 

@@ -1146,16 +1146,31 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
 static const uint2* dft_slots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.d_slots : ap.d_slots_dft; }
 static int dft_nslots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.n_slots : ap.n_slots_dft; }
 
-static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64_t n_samples, const float2* u,
-                      int64_t t_cal, float* image, hipStream_t s, float* partial, int splits, bool timed = true) {
-  const HostArray& h = ap.h;
-  const int N = h.nx;
+// Whether the array is imaged by the DFT-GEMM form (tuned or plan transform).
+static bool uses_dft(epic_plan_t plan, const ArrayPlan& ap) {
   const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
-  const bool dft = tr == 2 && epic::dft_supported(N, h.na, dft_nslots(ap));
+  return tr == 2 && epic::dft_supported(ap.h.nx, ap.h.na, dft_nslots(ap));
+}
+
+// The imaging arguments of one array: the FFT engines' schedules, or the
+// DFT-GEMM engine's.
+static ImageArgs image_args(epic_plan_t plan, const ArrayPlan& ap, const void* efield, int64_t n_samples,
+                            const float2* u, int64_t t_cal, float* partial, int splits) {
+  const HostArray& h = ap.h;
+  const bool dft = uses_dft(plan, ap);
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
                dft ? dft_slots(ap) : ap.d_slots, dft ? dft_nslots(ap) : ap.n_slots, splits, partial,
                ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
   with_dense_slots(ia, ap);
+  return ia;
+}
+
+static int image_pass(epic_plan_t plan, ArrayPlan& ap, const void* efield, int64_t n_samples, const float2* u,
+                      int64_t t_cal, float* image, hipStream_t s, float* partial, int splits, bool timed = true) {
+  const HostArray& h = ap.h;
+  const int N = h.nx;
+  const bool dft = uses_dft(plan, ap);
+  const ImageArgs ia = image_args(plan, ap, efield, n_samples, u, t_cal, partial, splits);
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     hipError_t e = dft ? epic::launch_image_dft(N, ia, s) : epic::launch_image(N, ia, s);
@@ -1180,39 +1195,21 @@ struct RunLayout {
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-static int engine_of(epic_plan_t plan, const ArrayPlan& ap) {
-  const HostArray& h = ap.h;
-  const int N = h.nx;
-  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
-  if (N >= 128) {
-    if (tr == 2 && epic::dft_supported(N, h.na, ap.n_slots)) return epic::engine_code(epic::kEngDftCls, N, N / 64);
-    const int v = epic::cls_variant(h.na, ap.n_slots);
-    return epic::engine_code(v == 2 ? epic::kEngClsBig : epic::kEngCls, N, N / 64);
-  }
-  const int apl = (h.na + 63) / 64 <= 2 ? 2 : (h.na + 63) / 64 <= 4 ? 4 : 8;
-  if (tr == 2 && epic::dft_supported(N, h.na, ap.n_slots_dft)) return epic::engine_code(epic::kEngDft, N, apl);
-  const int aplf = (h.na + N - 1) / N <= 2 ? 2 : (h.na + N - 1) / N <= 4 ? 4 : 8;
-  return epic::engine_code(epic::kEngFft, N, aplf);
-}
-
 static int solve_ps(const HostArray& h) {
   const int RB = h.na * epic::efmt_bytes(h.efmt);
   return RB % 16 == 0 ? 16 : RB % 4 == 0 ? 4 : 1;
 }
 
-// Arrays whose FFT engine has a two-waves-per-SIMD form (512-thread
-// workgroups) are imaged by their own launch in the batched form: the
-// persistent kernel runs 256-thread engine bodies.  So are the dense class
-// arrays (slot table in memory): their own kernel grids in batches of slots,
-// which the persistent kernel's body does not (there it measured slower).
-static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) {
-  const int code = engine_of(plan, ap), N = ap.h.nx;
-  const ImageArgs ia = engine_probe(ap);
-  if (code / 100 == epic::kEngFft) return epic::pair_engine(ia, N);
-  if (code / 100 == epic::kEngCls) return epic::cls_pair_engine(ia, N);
-  if (code / 100 == epic::kEngClsBig || code / 100 == epic::kEngDftCls) return true;
-  return false;
+// The persistent batched kernel's body for an array (0: the array is imaged
+// by its own launch in the batched sequence: complex float E-fields at 64 x 64
+// and above, the one-wave class engines, the DFT-GEMM form).
+static int body_of(epic_plan_t plan, const ArrayPlan& ap) {
+  ImageArgs ia = engine_probe(ap);
+  ia.n_slots = ap.n_slots;
+  return epic::batch_body(ia, ap.h.nx, uses_dft(plan, ap));
 }
+
+static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) { return body_of(plan, ap) == 0; }
 
 // Work items {array, channel, class group, split}, most expensive first;
 // none for the arrays with their own launch.
@@ -1229,7 +1226,7 @@ static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int6
   for (size_t i = 0; i < lay.size(); ++i) {
     if (own_launch(plan, plan->arrays[i])) continue;
     const HostArray& h = plan->arrays[i].h;
-    const int N = h.nx, cg = N == 256 ? 4 : 1;
+    const int N = h.nx, cg = units_for(plan->arrays[i]);
     const double per_frame = double(N) * N * std::log2(double(N) * N) / cg + 32.0 * h.na;
     for (int s = 0; s < lay[i].splits; ++s) {
       const int64_t tb = n_samples * s / lay[i].splits, te = n_samples * (s + 1) / lay[i].splits;
@@ -1381,22 +1378,17 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
       if (e != hipSuccess) return hip_fail(e, "gain history conversion launch");
     }
   }
-  // imaging: the arrays with a two-waves-per-SIMD engine or a dense class
-  // engine by their own launches, the others by one persistent launch over
-  // their work items
+  // imaging: one persistent launch over the work items of every array a body
+  // of the batched kernel covers; the others by their own launches
   {
     Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
     for (int i = 0; i < na_arr; ++i) {
       ArrayPlan& ap = plan->arrays[i];
       if (!own_launch(plan, ap)) continue;
-      const HostArray& h = ap.h;
-      const bool dft = engine_of(plan, ap) / 100 == epic::kEngDftCls;
-      ImageArgs ia{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt,
-                   reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal, ap.d_slots, ap.n_slots,
-                   lay[i].splits, reinterpret_cast<float*>(scr + lay[i].p_off), ap.d_slots_h, ap.n_slots_h0,
-                   ap.n_slots_h1};
-      with_dense_slots(ia, ap);
-      hipError_t e = dft ? epic::launch_image_dft(h.nx, ia, s) : epic::launch_image(h.nx, ia, s);
+      const ImageArgs ia = image_args(plan, ap, efield[i], n_samples,
+                                      reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal,
+                                      reinterpret_cast<float*>(scr + lay[i].p_off), lay[i].splits);
+      hipError_t e = uses_dft(plan, ap) ? epic::launch_image_dft(ap.h.nx, ia, s) : epic::launch_image(ap.h.nx, ia, s);
       if (e != hipSuccess) return hip_fail(e, "imaging launch");
     }
   }
@@ -1405,14 +1397,9 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
     b.n_arrays = na_arr;
     for (int i = 0; i < na_arr; ++i) {
       ArrayPlan& ap = plan->arrays[i];
-      const HostArray& h = ap.h;
-      const int code = engine_of(plan, ap);
-      const bool dft = code / 100 == epic::kEngDft;
-      b.arr[i] = ImageArgs{static_cast<const uint8_t*>(efield[i]), n_samples, h.F, h.na, h.efmt,
-                           reinterpret_cast<const float2*>(scr + lay[i].u_off), ap.t_cal,
-                           dft ? ap.d_slots_dft : ap.d_slots, dft ? ap.n_slots_dft : ap.n_slots, lay[i].splits,
-                           reinterpret_cast<float*>(scr + lay[i].p_off)};
-      b.code[i] = code;
+      b.arr[i] = image_args(plan, ap, efield[i], n_samples, reinterpret_cast<const float2*>(scr + lay[i].u_off),
+                            ap.t_cal, reinterpret_cast<float*>(scr + lay[i].p_off), lay[i].splits);
+      b.code[i] = body_of(plan, ap);
     }
     b.items = plan->d_items;
     b.n_items = plan->n_items;
@@ -1472,7 +1459,6 @@ static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_sa
                                                 : pick_splits(plan, ap, n_samples, ap.tune_splits);
     rc = layout_array(ap, n_samples, sp, size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
-    all_batchable = all_batchable && epic::batch_engine_supported(engine_of(plan, ap));
   }
   return EPIC_OK;
 }

@@ -139,13 +139,10 @@ struct AdjointArgs {
 
 // Batched execution over several arrays (one launch per stage).
 constexpr int kMaxBatch = 16;
-enum : int { kEngFft = 0, kEngDft = 1, kEngCls = 2, kEngClsBig = 3, kEngDftCls = 4 };
-// Engine code of an array: 100 * engine + (N / 32) * 10 + (APL or R).
-inline int engine_code(int engine, int N, int param) { return 100 * engine + (N / 32) * 10 + param; }
 
 struct BatchImageArgs {
   ImageArgs arr[kMaxBatch];
-  int code[kMaxBatch];
+  int code[kMaxBatch];      // body of each array (batch_body)
   int n_arrays;
   const int4* items;        // {array, channel, class group, split}, largest first
   int n_items;
@@ -168,7 +165,9 @@ struct BatchReduceArgs {
   int n_arrays;
 };
 
-bool batch_engine_supported(int code);
+// Body of the persistent batched imaging kernel for an array (0: none, the
+// array is imaged by its own launch in the batched sequence).
+int batch_body(const ImageArgs& a, int N, bool dft);
 hipError_t launch_image_batch(const BatchImageArgs& b, int n_workgroups, hipStream_t s);
 hipError_t launch_solve_batch(const BatchSolveArgs& b, int j, int ps, hipStream_t s);
 hipError_t launch_reduce_batch(const BatchReduceArgs& b, hipStream_t s);
@@ -195,6 +194,7 @@ bool image_supported(int N, int na, int n_slots);
 bool pair_engine(const ImageArgs& a, int N);   // the 64 x 64 two-waves-per-SIMD engine applies
 bool cls_pair_engine(const ImageArgs& a, int N);   // the 128 / 256 two-waves-per-SIMD class engine applies
 bool cls_dense_engine(const ImageArgs& a, int N);  // the dense two-waves-per-SIMD class engine applies
+bool cls_pair_db(const ImageArgs& a, int N);       // the class-pair engine's double-buffered form applies
 // Imaging workgroups per (channel, time split) of launch_image at N = 128, 256
 // (class groups); 1 below.
 int cls_groups(const ImageArgs& a, int N);

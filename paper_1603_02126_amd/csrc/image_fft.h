@@ -6,21 +6,23 @@
 
 namespace epic {
 
-// LDS layout of the FFT engine: frame buffers, E' staging, slot table.
-template <int N, int APL>
+// LDS layout of the FFT engine with W waves: frame buffers, E' staging, slot table.
+template <int N, int APL, int W = 4>
 struct FftSmem {
-  static constexpr int E_OFF = Geo<N>::LDS * 8;
-  static constexpr int T_OFF = E_OFF + Geo<N>::SLOTS * APL * N * 8;
-  static constexpr int BYTES = T_OFF + Budget<N, APL>::TAB_SLOTS * N * 8;
+  static constexpr int E_OFF = Geo<N, W>::LDS * 8;
+  static constexpr int T_OFF = E_OFF + Geo<N, W>::SLOTS * APL * N * 8;
+  static constexpr int BYTES = T_OFF + Budget<N, APL, W>::TAB_SLOTS * N * 8;
 };
 
-// One work item of the N <= 64 FFT engine: channel f, time split s.
-template <int N, int APL>
+// One work item of the N <= 64 FFT engine: channel f, time split s; W waves
+// (4 in its own kernel; 8, two per SIMD, in the persistent batched kernel,
+// for N <= 32 where eight waves' frame buffers fit).
+template <int N, int APL, int W = 4>
 __device__ __forceinline__ void image_item(const ImageArgs& a, int f, int s, uint8_t* smem) {
-  using G = Geo<N>;
+  using G = Geo<N, W>;
   float2* lds = reinterpret_cast<float2*>(smem);
-  float2* lds_e = reinterpret_cast<float2*>(smem + FftSmem<N, APL>::E_OFF);
-  uint2* stab = reinterpret_cast<uint2*>(smem + FftSmem<N, APL>::T_OFF);
+  float2* lds_e = reinterpret_cast<float2*>(smem + FftSmem<N, APL, W>::E_OFF);
+  uint2* stab = reinterpret_cast<uint2*>(smem + FftSmem<N, APL, W>::T_OFF);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane / N, lam = lane % N;
   const int slot = wave * G::FPW + h;
@@ -66,7 +68,7 @@ __device__ __forceinline__ void image_item(const ImageArgs& a, int f, int s, uin
   });
   __syncthreads();
   float* out = a.partial + (int64_t(s) * a.F + f) * (N * N);
-  for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+  for (int idx = threadIdx.x; idx < N * N; idx += 64 * W) {
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < G::SLOTS; ++q) sum += red[q * N * N + idx];

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
 
 template <int APL, int FMT>
 __global__ __launch_bounds__(kPairThreads) void k_image_pair(ImageArgs a) {
-  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  static_assert(APL == 2 || APL == 4, "instantiated for the register budget checked at two and four antennas per lane");
   __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
   image_item_pair<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
@@ -54,14 +54,14 @@ __global__ __launch_bounds__(256) void k_image_snap(ImageArgs a) {
 
 template <int APL, int FMT>
 __global__ __launch_bounds__(kPairThreads) void k_image_pair_snap(ImageArgs a) {
-  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  static_assert(APL == 2 || APL == 4, "instantiated for the register budget checked at two and four antennas per lane");
   __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
   image_item_pair_snap<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
 
 template <int APL, int FMT>
 __global__ __launch_bounds__(kPairThreads) void k_image_pair_snap_group(ImageArgs a) {
-  static_assert(APL == 4, "instantiated for the register budget checked at four antennas per lane");
+  static_assert(APL == 2 || APL == 4, "instantiated for the register budget checked at two and four antennas per lane");
   __shared__ __align__(16) uint8_t smem[PairSmem<APL>::BYTES];
   image_item_pair_snap_group<APL, FMT>(a, blockIdx.x % a.F, blockIdx.x / a.F, smem);
 }
@@ -241,18 +241,19 @@ bool image_supported(int N, int na, int n_slots) {
   return apl != 0 && n_slots <= tab_slots_for(N, apl);
 }
 
-// The paired 64 x 64 engine: integer E-fields, 129..256 antennas (four per
-// lane: the register budget of two waves per SIMD is checked there), and a
-// half-frame schedule that fits its LDS table.
+// The paired 64 x 64 engine: integer E-fields, up to 256 antennas (two or
+// four per lane: the register budget of two waves per SIMD is checked
+// there), and a half-frame schedule that fits its LDS table.
 bool pair_engine(const ImageArgs& a, int N) {
-  return N == 64 && a.fmt != kCF32 && apl_for(N, a.Na) == 4 && a.slots_h != nullptr &&
-         a.n_slots_h0 + a.n_slots_h1 <= PairSmem<4>::TAB_SLOTS;
+  const int apl = apl_for(N, a.Na);
+  return N == 64 && a.fmt != kCF32 && (apl == 2 || apl == 4) && a.slots_h != nullptr &&
+         a.n_slots_h0 + a.n_slots_h1 <= (apl == 2 ? PairSmem<2>::TAB_SLOTS : PairSmem<4>::TAB_SLOTS);
 }
 
 template <int N, int APL>
 struct LaunchImage {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
-    if constexpr (N == 64 && APL == 4) {
+    if constexpr (N == 64 && (APL == 2 || APL == 4)) {
       if (pair_engine(a, N)) {
         if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_pair<APL, kCI4>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
         else hipLaunchKernelGGL((k_image_pair<APL, kCI8>), dim3(a.F * a.splits), dim3(kPairThreads), 0, s, a);
@@ -268,7 +269,7 @@ struct LaunchImage {
 // most 512 antennas, half-frame schedules that fit its LDS table; with at
 // most kClsPairMaxAntDB antennas and a table that still fits, its
 // double-buffered form (one barrier per pair of samples).
-static bool cls_pair_db(const ImageArgs& a, int N) {
+bool cls_pair_db(const ImageArgs& a, int N) {
   const int cap = N == 128 ? ClsPairSmem<2, true>::TAB_SLOTS : ClsPairSmem<4, true>::TAB_SLOTS;
   return a.Na <= kClsPairMaxAntDB && a.n_slots_h0 + a.n_slots_h1 <= cap;
 }
@@ -331,7 +332,7 @@ hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
 template <int N, int APL>
 struct LaunchImageSnap {
   static hipError_t run(const ImageArgs& a, hipStream_t s) {
-    if constexpr (N == 64 && APL == 4) {
+    if constexpr (N == 64 && (APL == 2 || APL == 4)) {
       if (pair_engine(a, N)) {
         const dim3 grid(a.F * a.splits), block(kPairThreads);
         if (a.t_acc >= kSnapGroupWindow) {

@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 from paper_1603_02126_amd import synth  # noqa: E402
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published dense FP32 vector peak
-PEAK_FP16_MFMA_TFLOPS = 2500.0    # MI355X published dense FP16 matrix peak
+PEAK_FP16_MFMA_TFLOPS = 2500.0    # MI355X published dense FP16 / BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the imaging kernel on the LWA-shaped workload (averaged
@@ -91,12 +91,17 @@ def measured_traffic(workload_name):
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0
 
 
-def dft_mfma_flops_per_frame(n):
+def dft_mfma_flops_per_frame(n, products=3):
     """Executed matrix-core flops of the split-precision DFT-GEMM per frame:
-    two complex M x M x M products, four real GEMMs each, three split terms,
-    for each of the (n / M)^2 residue classes of 64 x 64 (M = min(n, 64))."""
+    two complex M x M x M products, four real GEMMs each, `products` part
+    products per real GEMM (3 for hi + lo, 6 for hi + mid + lo), for each of
+    the (n / M)^2 residue classes of 64 x 64 (M = min(n, 64))."""
     m = min(n, 64)
-    return (n // m) ** 2 * 2 * 4 * 3 * 2 * m ** 3
+    return (n // m) ** 2 * 2 * 4 * products * 2 * m ** 3
+
+
+# the DFT-GEMM forms: (name, EPIC_OPT_TRANSFORM value, part products per real product)
+DFT_FORMS = (("dft_gemm_fp16_split", 2, 3), ("dft_gemm_bf16_split", 3, 3), ("dft_gemm_bf16x3_split", 4, 6))
 
 
 def imaging_flops_per_frame(n, na, k2):
@@ -447,24 +452,26 @@ def bench_single(args, dev):
     frames = a.n_chan * wl.n_samples
     forms = {}
     if not args.no_forms:
-        if a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512):
+        for name, tr, prods in DFT_FORMS:
+            if not (a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512)):
+                forms[name] = {"supported": False, "reason": "the DFT-GEMM form covers arrays of at most 512 antennas"}
+                continue
             # form 1: split-precision DFT-GEMM on the matrix cores, same workload
-            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: 2}, pix, band)
+            plan_d = new_plan([wl], {lib.OPT_TRANSFORM: tr}, pix, band)
             img_d = torch.zeros_like(img)
             dt_d, tim_d = Timer([plan_d])(stepper(plan_d, img_d), args.steps, args.warmup)
             ms_img_d = tim_d[lib.TIMER_IMAGE][0] / max(1, tim_d[lib.TIMER_IMAGE][1])
-            mf = dft_mfma_flops_per_frame(a.nx) * frames / (ms_img_d * 1e-3) / 1e12
-            forms["dft_gemm_fp16_split"] = {
+            mf = dft_mfma_flops_per_frame(a.nx, prods) * frames / (ms_img_d * 1e-3) / 1e12
+            forms[name] = {
                 "ms_per_step": dt_d / args.steps * 1e3, "frames_per_s": frames / (dt_d / args.steps),
                 "speedup_vs_plain": dt / dt_d, "imaging_kernel_ms": ms_img_d,
-                "mfma": {"achieved": mf, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s (executed, fp16)",
+                "mfma": {"achieved": mf, "peak": PEAK_FP16_MFMA_TFLOPS,
+                         "unit": "TFLOP/s (executed, " + ("fp16" if tr == 2 else "bf16") + ")",
                          "frac": mf / PEAK_FP16_MFMA_TFLOPS},
                 "max_rel_diff_vs_plain": rel_err(img_d.cpu().numpy(), img.cpu().numpy()),
+                "gains": "identical to the plain path (the FP64 solve does not depend on the transform)",
                 "_image": img_d}
             plan_d.close()
-        else:
-            forms["dft_gemm_fp16_split"] = {"supported": False,
-                                             "reason": "the DFT-GEMM form covers arrays of at most 512 antennas"}
     # form 2: batched launches captured in a hipGraph, after autotuning
     if not args.no_forms and band is not None:
         forms["batched_graph_autotuned"] = {"supported": False,

@@ -236,11 +236,15 @@ int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
 
 /* Options (key, value).  Keys:
  *   EPIC_OPT_SPLITS      time splits per channel of the imaging launch (0 = auto)
- *   EPIC_OPT_TRANSFORM   0 = FFT, 1 = FFT (FP32), 2 = DFT-GEMM (FP16 hi+lo split on
- *                        the matrix cores, FP32 accumulation; grids 32 and 64,
- *                        and 128 and 256 as residue classes of 64 x 64 DFT-GEMMs
- *                        for arrays of at most 512 antennas; those are imaged
- *                        with one launch per array even when batched)
+ *   EPIC_OPT_TRANSFORM   0 = FFT, 1 = FFT (FP32), or the 2D DFT as two complex
+ *                        GEMMs on the matrix cores with split 16-bit operands
+ *                        and FP32 accumulation: 2 = fp16 hi + lo (three part
+ *                        products, ~22 bits), 3 = bf16 hi + lo (three, ~16 bits),
+ *                        4 = bf16 hi + mid + lo (six, ~24 bits).  Grids
+ *                        32 and 64 (up to 512 antennas), and 128 and 256 as
+ *                        residue classes of 64 x 64 DFT-GEMMs (up to 512
+ *                        antennas); imaged with one launch per array even when
+ *                        batched.  Arrays the DFT-GEMM does not cover use the FFT.
  *   EPIC_OPT_TIMING      1 = record HIP events around each kernel (see below)
  *   EPIC_OPT_BATCH       0 = batched when the plan has several arrays, 1 = always
  *                        batched, 2 = never.  Batched, epic_run makes one launch per
@@ -272,15 +276,15 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 #define EPIC_TIMER_COUNT 5
 
 /* Autotuner: for every array, time the imaging launch of the given E-field
- * stream (n_samples samples) with each candidate transform (FFT; DFT-GEMM for
- * the grids and arrays it covers) and time-split count, and keep the fastest for
- * later runs.
+ * stream (n_samples samples) with each candidate transform (FFT; for the grids
+ * and arrays the DFT-GEMM covers, its three precisions) and time-split count,
+ * and keep the fastest for later runs.
  * Synchronous (waits for the device); efield: one device pointer per array. */
 int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples,
                        epic_stream_t stream);
 
-/* Tuning state per array: tuning[3 i + 0] = transform (1 FFT, 2 DFT-GEMM,
- * 0 = plan default), [3 i + 1] = time splits (0 = auto), [3 i + 2] = measured
+/* Tuning state per array: tuning[3 i + 0] = transform (EPIC_OPT_TRANSFORM
+ * values 1..4, 0 = plan default), [3 i + 1] = time splits (0 = auto), [3 i + 2] = measured
  * imaging time in microseconds (get only).  Host arrays of 3 * n_arrays. */
 int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning);
 int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning);

@@ -346,8 +346,8 @@ int build_slots_cls(const HostArray& h, std::vector<uint32_t>& table, int half =
 }
 
 // Multi-class schedule of the dense residue-class engine (N = 64 R): the
-// sub-cells q = j mod 64 of sub-cell columns [32 half, 32 half + 32) are
-// balanced over `owners` lanes (all waves of a frame); a lane's slots of one
+// sub-cells q = j mod 64 of sub-cell columns [32 half, 32 half + 32) (all
+// columns for half < 0) are balanced over `owners` lanes (all waves of a frame); a lane's slots of one
 // sub-cell are consecutive, the first marked first, the last marked last.
 // Padding slots: weight 0, first, not last.
 int build_slots_dense(const HostArray& h, int owners, int half, std::vector<uint32_t>& table) {
@@ -360,7 +360,7 @@ int build_slots_dense(const HostArray& h, int owners, int half, std::vector<uint
     if (h.flag[a]) continue;
     for (int k = 0; k < h.k2; ++k) {
       const size_t q = size_t(a) * h.k2 + k;
-      if (w[q] == 0.0 || (ix[q] % 64) / 32 != half) continue;
+      if (w[q] == 0.0 || (half >= 0 && (ix[q] % 64) / 32 != half)) continue;
       sub[size_t(iy[q] % 64) * 64 + ix[q] % 64].push_back({a, ix[q], iy[q], float(w[q])});
     }
   }
@@ -464,6 +464,8 @@ struct ArrayPlan {
   int n_slots_h0 = 0, n_slots_h1 = 0;
   uint2* d_slots_m = nullptr;     // 128 / 256, integer formats: multi-class schedules (two halves)
   int n_slots_m0 = 0, n_slots_m1 = 0;
+  uint2* d_slots_c = nullptr;     // 128 / 256: class schedule of the DFT-GEMM engine (128 owners)
+  int n_slots_c = 0;
   uint8_t* d_flag = nullptr;
   // tuning (0 = plan default): transform 1 FFT / 2 DFT-GEMM, time splits
   int tune_transform = 0;
@@ -536,6 +538,7 @@ void free_array(ArrayPlan& p) {
   hipFree(p.d_slots_dft);
   hipFree(p.d_slots_h);
   hipFree(p.d_slots_m);
+  hipFree(p.d_slots_c);
   hipFree(p.d_flag);
   hipFree(p.d_k0);
   hipFree(p.d_A);
@@ -823,7 +826,7 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
       ap.n_slots = build_slots(ap.h, L, epic::grid_pitch(ap.h.nx), tab);
       rc = upload(&ap.d_slots, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       if (!rc && (ap.h.nx == 32 || ap.h.nx == 64)) {
-        ap.n_slots_dft = build_slots(ap.h, 64, ap.h.nx + 2, tab, true);
+        ap.n_slots_dft = build_slots(ap.h, epic::dft_owners(ap.h.nx), ap.h.nx + 2, tab, true);
         rc = upload(&ap.d_slots_dft, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }
       if (!rc && ap.h.nx == 64) {
@@ -843,6 +846,10 @@ int epic_plan_create(const epic_array_desc* arrays, int32_t n_arrays, epic_plan_
         ap.n_slots_h1 = build_slots_cls(ap.h, hi, 1);
         tab.insert(tab.end(), hi.begin(), hi.end());
         rc = upload(&ap.d_slots_h, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
+      }
+      if (!rc) {
+        ap.n_slots_c = build_slots_dense(ap.h, epic::dft_owners(ap.h.nx), -1, tab);
+        rc = upload(&ap.d_slots_c, reinterpret_cast<const uint2*>(tab.data()), tab.size() / 2);
       }
       if (!rc && ap.h.efmt != EPIC_CF32) {
         std::vector<uint32_t> hi;
@@ -1041,7 +1048,7 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
       plan->generation++;
       return EPIC_OK;
     case EPIC_OPT_TRANSFORM:
-      if (value < 0 || value > 2) return fail(EPIC_ERR_ARG, "transform must be 0, 1 or 2");
+      if (value < 0 || value > 4) return fail(EPIC_ERR_ARG, "transform must be in 0..4");
       plan->transform = int(value);
       plan->generation++;
       return EPIC_OK;
@@ -1143,13 +1150,15 @@ int epical_update(epic_plan_t plan, int32_t array, const void* efield, int64_t t
 
 // Slot schedule of the DFT-GEMM engine: its own transposed table for N <= 64,
 // the residue-class table for N = 128, 256.
-static const uint2* dft_slots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.d_slots : ap.d_slots_dft; }
-static int dft_nslots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.n_slots : ap.n_slots_dft; }
+static const uint2* dft_slots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.d_slots_c : ap.d_slots_dft; }
+static int dft_nslots(const ArrayPlan& ap) { return ap.h.nx >= 128 ? ap.n_slots_c : ap.n_slots_dft; }
 
 // Whether the array is imaged by the DFT-GEMM form (tuned or plan transform).
+static int transform_of(epic_plan_t plan, const ArrayPlan& ap) {
+  return ap.tune_transform ? ap.tune_transform : plan->transform;
+}
 static bool uses_dft(epic_plan_t plan, const ArrayPlan& ap) {
-  const int tr = ap.tune_transform ? ap.tune_transform : plan->transform;
-  return tr == 2 && epic::dft_supported(ap.h.nx, ap.h.na, dft_nslots(ap));
+  return transform_of(plan, ap) >= 2 && epic::dft_supported(ap.h.nx, ap.h.na, dft_nslots(ap));
 }
 
 // The imaging arguments of one array: the FFT engines' schedules, or the
@@ -1159,9 +1168,14 @@ static ImageArgs image_args(epic_plan_t plan, const ArrayPlan& ap, const void* e
   const HostArray& h = ap.h;
   const bool dft = uses_dft(plan, ap);
   ImageArgs ia{static_cast<const uint8_t*>(efield), n_samples, h.F, h.na, h.efmt, u, t_cal,
-               dft ? dft_slots(ap) : ap.d_slots, dft ? dft_nslots(ap) : ap.n_slots, splits, partial,
-               ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
+               dft && h.nx <= 64 ? dft_slots(ap) : ap.d_slots, dft && h.nx <= 64 ? dft_nslots(ap) : ap.n_slots,
+               splits, partial, ap.d_slots_h, ap.n_slots_h0, ap.n_slots_h1};
   with_dense_slots(ia, ap);
+  if (dft) {
+    ia.dft_prec = transform_of(plan, ap) - 2;
+    ia.slots_c = ap.d_slots_c;
+    ia.n_slots_c = ap.n_slots_c;
+  }
   return ia;
 }
 
@@ -1710,8 +1724,10 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
     if (!efield[i]) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
     if ((rc = check_aligned({{efield[i], "efield"}}))) return rc;
     const HostArray& h = ap.h;
+    // candidates: the FFT and the three DFT-GEMM precisions
     std::vector<int> trs{1};
-    if (epic::dft_supported(h.nx, h.na, dft_nslots(ap))) trs.push_back(2);
+    if (epic::dft_supported(h.nx, h.na, dft_nslots(ap)))
+      for (int t : {2, 3, 4}) trs.push_back(t);
     const int base = pick_splits(plan, ap, n_samples, 0);
     std::vector<int> sps;
     for (int c : {base / 2, base, 2 * base, 4 * base}) {
@@ -1789,7 +1805,7 @@ int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning) {
 int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning) {
   if (!plan || !tuning) return fail(EPIC_ERR_ARG, "plan and tuning must not be NULL");
   for (size_t i = 0; i < plan->arrays.size(); ++i)
-    if (tuning[3 * i] < 0 || tuning[3 * i] > 2 || tuning[3 * i + 1] < 0)
+    if (tuning[3 * i] < 0 || tuning[3 * i] > 4 || tuning[3 * i + 1] < 0)
       return fail(EPIC_ERR_ARG, "bad tuning entry for array %zu", i);
   for (size_t i = 0; i < plan->arrays.size(); ++i) {
     plan->arrays[i].tune_transform = tuning[3 * i];

@@ -43,6 +43,12 @@ struct ImageArgs {
   // owners; null when not built
   const uint2* slots_m = nullptr;
   int n_slots_m0 = 0, n_slots_m1 = 0;
+  // DFT-GEMM form: operand precision (0 fp16 hi + lo, 1 bf16 hi + lo, 2 bf16
+  // hi + mid + lo) and, for N = 128, 256, its class schedule (128 owners, all
+  // sub-cell columns, the dense engine's slot format)
+  int dft_prec = 0;
+  const uint2* slots_c = nullptr;
+  int n_slots_c = 0;
 };
 
 // Stage-wise gridding to HBM.
@@ -198,8 +204,10 @@ bool cls_pair_db(const ImageArgs& a, int N);       // the class-pair engine's do
 // Imaging workgroups per (channel, time split) of launch_image at N = 128, 256
 // (class groups); 1 below.
 int cls_groups(const ImageArgs& a, int N);
-// Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64; its gridding
-// schedule has 64 lanes and transposed (G^T) cell offsets.
+// Split-precision DFT-GEMM imaging (matrix cores), N = 32 or 64 directly (its
+// gridding schedule has 64 N / 32 lanes and transposed (G^T) cell offsets),
+// N = 128, 256 by residue classes (the class schedule slots_c).
+int dft_owners(int N);
 bool dft_supported(int N, int na, int n_slots);
 hipError_t launch_image_dft(int N, const ImageArgs& a, hipStream_t s);
 hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s);

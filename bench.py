@@ -100,6 +100,8 @@ def dft_mfma_flops_per_frame(n, products=3):
     return (n // m) ** 2 * 2 * 4 * products * 2 * m ** 3
 
 
+TRANSFORM_NAMES = ["default", "fft", "dft_gemm_fp16_split", "dft_gemm_bf16_split", "dft_gemm_bf16x3_split"]
+
 # the DFT-GEMM forms: (name, EPIC_OPT_TRANSFORM value, part products per real product)
 DFT_FORMS = (("dft_gemm_fp16_split", 2, 3), ("dft_gemm_bf16_split", 3, 3), ("dft_gemm_bf16x3_split", 4, 6))
 
@@ -486,7 +488,8 @@ def bench_single(args, dev):
         forms["batched_graph_autotuned"] = {
             "ms_per_step": dt_g / args.steps * 1e3, "frames_per_s": frames / (dt_g / args.steps),
             "speedup_vs_plain": dt / dt_g,
-            "tuning": {"transform": ["", "fft", "dft_gemm"][tuning[0][0]], "splits": tuning[0][1]},
+            "tuning": {"transform": TRANSFORM_NAMES[tuning[0][0]], "splits": tuning[0][1],
+                       "grid_batch": tuning[0][2]},
             "graph_replay_ms": tim_g[lib.TIMER_GRAPH][0] / max(1, tim_g[lib.TIMER_GRAPH][1]),
             "max_rel_diff_vs_plain": rel_err(img_g.cpu().numpy(), img.cpu().numpy()),
             "_image": img_g}
@@ -686,7 +689,8 @@ def bench_uneven(args, dev):
             "ms_per_step": dt_g / args.steps * 1e3, "frames_per_s": frames / (dt_g / args.steps),
             "speedup_vs_plain": dt / dt_g,
             "tuning": [{"grid": w.array.nx, "n_ant": w.array.n_ant,
-                        "transform": ["", "fft", "dft_gemm"][t[0]], "splits": t[1]} for w, t in zip(wls, tuning)],
+                        "transform": TRANSFORM_NAMES[t[0]], "splits": t[1], "grid_batch": t[2]}
+                       for w, t in zip(wls, tuning)],
             "graph_replay_ms": tim_g[lib.TIMER_GRAPH][0] / max(1, tim_g[lib.TIMER_GRAPH][1]),
             "max_rel_diff_vs_plain": max(rel_err(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(imgs_g, imgs)),
             "_images": imgs_g}

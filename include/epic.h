@@ -106,7 +106,7 @@ typedef struct {
 /* Library information and host-only helpers (no device needed)           */
 /* ---------------------------------------------------------------------- */
 
-/* ABI version, currently 1. */
+/* ABI version, currently 2 (2: tuning records of four values). */
 int32_t epic_abi_version(void);
 
 /* Message describing the last error on this thread ("" if none).  Valid until
@@ -277,15 +277,28 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 
 /* Autotuner: for every array, time the imaging launch of the given E-field
  * stream (n_samples samples) with each candidate transform (FFT; for the grids
- * and arrays the DFT-GEMM covers, its three precisions) and time-split count,
- * and keep the fastest for later runs.
+ * and arrays the DFT-GEMM covers, its three precisions), time-split count
+ * (frames per workgroup) and, for the dense residue-class engine, gridding
+ * batch (2 or 4 slots), and keep the fastest for later runs.
  * Synchronous (waits for the device); efield: one device pointer per array. */
 int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples,
                        epic_stream_t stream);
 
-/* Tuning state per array: tuning[3 i + 0] = transform (EPIC_OPT_TRANSFORM
- * values 1..4, 0 = plan default), [3 i + 1] = time splits (0 = auto), [3 i + 2] = measured
- * imaging time in microseconds (get only).  Host arrays of 3 * n_arrays. */
+/* epic_plan_autotune with a tuning cache: cache_path (host string) names a
+ * JSON file of entries keyed by the GPU architecture, grid size, antenna
+ * count, kernel, sample format, channel count and n_samples.  Arrays with an
+ * entry take it without timing; the others are timed and their entries
+ * added (the file is rewritten then).  A missing file starts an empty
+ * cache; lines that are not entries of this format are ignored.  NULL
+ * cache_path is epic_plan_autotune. */
+int epic_plan_autotune_cached(epic_plan_t plan, const void* const* efield, int64_t n_samples,
+                              const char* cache_path, epic_stream_t stream);
+
+/* Tuning state per array: tuning[4 i + 0] = transform (EPIC_OPT_TRANSFORM
+ * values 1..4, 0 = plan default), [4 i + 1] = time splits (0 = auto),
+ * [4 i + 2] = dense class engine gridding batch (0 or 2 = default, 4),
+ * [4 i + 3] = measured imaging time in microseconds (get only).  Host arrays
+ * of 4 * n_arrays. */
 int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning);
 int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning);
 int epic_plan_get_timing(epic_plan_t plan, double* ms, int64_t* launches, int32_t n);

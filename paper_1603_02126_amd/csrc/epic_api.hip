@@ -470,6 +470,7 @@ struct ArrayPlan {
   // tuning (0 = plan default): transform 1 FFT / 2 DFT-GEMM, time splits
   int tune_transform = 0;
   int tune_splits = 0;
+  int tune_batch = 0;          // dense class engine gridding batch (0 = default)
   double tune_us = 0;
   bool has_model = false;
   double gamma = 0;
@@ -647,6 +648,7 @@ void with_dense_slots(ImageArgs& ia, const ArrayPlan& ap) {
   ia.slots_m = ap.d_slots_m;
   ia.n_slots_m0 = ap.n_slots_m0;
   ia.n_slots_m1 = ap.n_slots_m1;
+  ia.grid_batch = ap.tune_batch;
 }
 
 // The fields of an array's imaging arguments that decide which engine runs it.
@@ -690,7 +692,7 @@ int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0) {
 
 extern "C" {
 
-int32_t epic_abi_version(void) { return 1; }
+int32_t epic_abi_version(void) { return 2; }
 
 const char* epic_last_error(void) { return g_err.c_str(); }
 
@@ -1711,49 +1713,55 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "adjoint reduction launch");
 }
 
-int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples, epic_stream_t stream) {
-  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
-  if (!efield) return fail(EPIC_ERR_ARG, "efield array is NULL");
-  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < int(plan->arrays.size()); ++i) {
-    int rc = check_plan(plan, i);
-    if (rc) return rc;
-    ArrayPlan& ap = plan->arrays[i];
-    if ((rc = check_grid_supported(ap))) return rc;
-    if (!efield[i]) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
-    if ((rc = check_aligned({{efield[i], "efield"}}))) return rc;
-    const HostArray& h = ap.h;
-    // candidates: the FFT and the three DFT-GEMM precisions
-    std::vector<int> trs{1};
-    if (epic::dft_supported(h.nx, h.na, dft_nslots(ap)))
-      for (int t : {2, 3, 4}) trs.push_back(t);
-    const int base = pick_splits(plan, ap, n_samples, 0);
-    std::vector<int> sps;
-    for (int c : {base / 2, base, 2 * base, 4 * base}) {
-      const int v = int(std::max<int64_t>(1, std::min<int64_t>(c, n_samples)));
-      if (std::find(sps.begin(), sps.end(), v) == sps.end()) sps.push_back(v);
-    }
-    const int max_sp = *std::max_element(sps.begin(), sps.end());
-    const size_t ub = align256(size_t(h.F) * h.na * sizeof(float2));
-    const size_t ib = align256(size_t(h.F) * h.nx * h.ny * sizeof(float));
-    void* scr = nullptr;
-    if ((rc = plan_scratch(plan, ub + ib + size_t(max_sp) * h.F * h.nx * h.ny * sizeof(float), &scr))) return rc;
-    char* base_p = static_cast<char*>(scr);
-    std::vector<float2> ones(size_t(h.F) * h.na, make_float2(1.f, 0.f));
-    hipError_t e = hipMemcpy(base_p, ones.data(), ones.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "autotune setup");
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(EPIC_ERR_HIP, "event");
-    int best_tr = 1, best_sp = base;
-    double best_us = 1e300;
-    const int keep_tr = ap.tune_transform, keep_sp = ap.tune_splits;
-    for (int tr : trs)
-      for (int sp : sps) {
-        ap.tune_transform = tr;
+// Time the candidate imaging launches of array i and keep the fastest
+// (transform, time splits, dense gridding batch).
+static int autotune_array(epic_plan_t plan, int i, const void* efield, int64_t n_samples, hipStream_t s) {
+  ArrayPlan& ap = plan->arrays[i];
+  int rc = check_grid_supported(ap);
+  if (rc) return rc;
+  if (!efield) return fail(EPIC_ERR_ARG, "NULL efield for array %d", i);
+  if ((rc = check_aligned({{efield, "efield"}}))) return rc;
+  const HostArray& h = ap.h;
+  // candidates: the FFT and the three DFT-GEMM precisions
+  std::vector<int> trs{1};
+  if (epic::dft_supported(h.nx, h.na, dft_nslots(ap)))
+    for (int t : {2, 3, 4}) trs.push_back(t);
+  const int base = pick_splits(plan, ap, n_samples, 0);
+  std::vector<int> sps;
+  for (int c : {base / 2, base, 2 * base, 4 * base}) {
+    const int v = int(std::max<int64_t>(1, std::min<int64_t>(c, n_samples)));
+    if (std::find(sps.begin(), sps.end(), v) == sps.end()) sps.push_back(v);
+  }
+  const int max_sp = *std::max_element(sps.begin(), sps.end());
+  const size_t ub = align256(size_t(h.F) * h.na * sizeof(float2));
+  const size_t ib = align256(size_t(h.F) * h.nx * h.ny * sizeof(float));
+  void* scr = nullptr;
+  if ((rc = plan_scratch(plan, ub + ib + size_t(max_sp) * h.F * h.nx * h.ny * sizeof(float), &scr))) return rc;
+  char* base_p = static_cast<char*>(scr);
+  std::vector<float2> ones(size_t(h.F) * h.na, make_float2(1.f, 0.f));
+  hipError_t e = hipMemcpy(base_p, ones.data(), ones.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "autotune setup");
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess) return fail(EPIC_ERR_HIP, "autotune event");
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return fail(EPIC_ERR_HIP, "autotune event");
+  }
+  int best_tr = 1, best_sp = base, best_gb = 0;
+  double best_us = 1e300;
+  const int keep_tr = ap.tune_transform, keep_sp = ap.tune_splits, keep_gb = ap.tune_batch;
+  for (int tr : trs)
+    for (int sp : sps) {
+      ap.tune_transform = tr;
+      ap.tune_batch = 0;
+      // the dense class engine's gridding batch (other engines size theirs from the schedule)
+      std::vector<int> gbs{0};
+      if (!uses_dft(plan, ap) && epic::cls_dense_engine(engine_probe(ap), h.nx)) gbs.push_back(4);
+      for (int gb : gbs) {
+        ap.tune_batch = gb;
         ap.tune_splits = sp;
         auto once = [&]() {
-          return image_pass(plan, ap, efield[i], n_samples, reinterpret_cast<const float2*>(base_p),
+          return image_pass(plan, ap, efield, n_samples, reinterpret_cast<const float2*>(base_p),
                             std::numeric_limits<int64_t>::max(), reinterpret_cast<float*>(base_p + ub), s,
                             reinterpret_cast<float*>(base_p + ub + ib), sp, false);
         };
@@ -1774,30 +1782,136 @@ int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_sa
           best_us = us;
           best_tr = tr;
           best_sp = sp;
+          best_gb = gb;
         }
       }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    if (rc) {
-      ap.tune_transform = keep_tr;
-      ap.tune_splits = keep_sp;
-      return rc;
+      if (rc) break;
     }
-    ap.tune_transform = best_tr;
-    ap.tune_splits = best_sp;
-    ap.tune_us = best_us;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (rc) {
+    ap.tune_transform = keep_tr;
+    ap.tune_splits = keep_sp;
+    ap.tune_batch = keep_gb;
+    return rc;
+  }
+  ap.tune_transform = best_tr;
+  ap.tune_splits = best_sp;
+  ap.tune_batch = best_gb;
+  ap.tune_us = best_us;
+  return EPIC_OK;
+}
+
+int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples, epic_stream_t stream) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (!efield) return fail(EPIC_ERR_ARG, "efield array is NULL");
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < int(plan->arrays.size()); ++i) {
+    int rc = check_plan(plan, i);
+    if (rc) return rc;
+    if ((rc = autotune_array(plan, i, efield[i], n_samples, s))) return rc;
   }
   plan->generation++;
   hipError_t e = hipStreamSynchronize(s);
   return e == hipSuccess ? EPIC_OK : hip_fail(e, "autotune synchronise");
 }
 
+// Tuning cache: one JSON object, one entry per line,
+//   "<arch>|N=<n>|Na=<na>|K=<k>|fmt=<fmt>|F=<f>|T=<t>": {"transform": t, "splits": s, "batch": b, "us": u}
+// keyed by everything the imaging launch's speed depends on.
+static std::string tune_key(const HostArray& h, int64_t n_samples, const char* arch) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|N=%d|Na=%d|K=%d|fmt=%d|F=%d|T=%lld", arch, h.nx, h.na, h.kernel, h.efmt, h.F,
+           (long long)n_samples);
+  return buf;
+}
+
+struct TuneEntry {
+  int transform, splits, batch;
+  double us;
+};
+
+static void read_tune_cache(const char* path, std::vector<std::pair<std::string, TuneEntry>>& out) {
+  out.clear();
+  FILE* fp = fopen(path, "r");
+  if (!fp) return;
+  char line[1024];
+  while (fgets(line, sizeof line, fp)) {
+    const char* q0 = strchr(line, '"');
+    const char* q1 = q0 ? strchr(q0 + 1, '"') : nullptr;
+    if (!q0 || !q1) continue;
+    TuneEntry t{};
+    const char* body = strchr(q1, '{');
+    if (!body || sscanf(body, "{\"transform\": %d, \"splits\": %d, \"batch\": %d, \"us\": %lf", &t.transform,
+                        &t.splits, &t.batch, &t.us) != 4)
+      continue;   // not an entry of this format: ignored (retuned)
+    if (t.transform < 1 || t.transform > 4 || t.splits < 1 || (t.batch != 0 && t.batch != 4)) continue;
+    out.push_back({std::string(q0 + 1, q1), t});
+  }
+  fclose(fp);
+}
+
+static int write_tune_cache(const char* path, const std::vector<std::pair<std::string, TuneEntry>>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fp = fopen(tmp.c_str(), "w");
+  if (!fp) return fail(EPIC_ERR_ARG, "cannot write the tuning cache %s", tmp.c_str());
+  fprintf(fp, "{\n");
+  for (size_t k = 0; k < entries.size(); ++k) {
+    const TuneEntry& t = entries[k].second;
+    fprintf(fp, "  \"%s\": {\"transform\": %d, \"splits\": %d, \"batch\": %d, \"us\": %.3f}%s\n",
+            entries[k].first.c_str(), t.transform, t.splits, t.batch, t.us, k + 1 < entries.size() ? "," : "");
+  }
+  fprintf(fp, "}\n");
+  const bool ok = fclose(fp) == 0 && rename(tmp.c_str(), path) == 0;
+  return ok ? EPIC_OK : fail(EPIC_ERR_ARG, "cannot write the tuning cache %s", path);
+}
+
+int epic_plan_autotune_cached(epic_plan_t plan, const void* const* efield, int64_t n_samples, const char* cache_path,
+                              epic_stream_t stream) {
+  if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
+  if (!cache_path) return epic_plan_autotune(plan, efield, n_samples, stream);
+  if (!efield) return fail(EPIC_ERR_ARG, "efield array is NULL");
+  if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, plan->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  std::vector<std::pair<std::string, TuneEntry>> cache;
+  read_tune_cache(cache_path, cache);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool added = false;
+  for (int i = 0; i < int(plan->arrays.size()); ++i) {
+    int rc = check_plan(plan, i);
+    if (rc) return rc;
+    ArrayPlan& ap = plan->arrays[i];
+    const std::string key = tune_key(ap.h, n_samples, arch.c_str());
+    auto it = std::find_if(cache.begin(), cache.end(), [&](const auto& kv) { return kv.first == key; });
+    if (it != cache.end()) {
+      ap.tune_transform = it->second.transform;
+      ap.tune_splits = it->second.splits;
+      ap.tune_batch = it->second.batch;
+      ap.tune_us = it->second.us;
+      continue;
+    }
+    if ((rc = autotune_array(plan, i, efield[i], n_samples, s))) return rc;
+    cache.push_back({key, TuneEntry{ap.tune_transform, ap.tune_splits, ap.tune_batch, ap.tune_us}});
+    added = true;
+  }
+  plan->generation++;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "autotune synchronise");
+  return added ? write_tune_cache(cache_path, cache) : EPIC_OK;
+}
+
 int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning) {
   if (!plan || !tuning) return fail(EPIC_ERR_ARG, "plan and tuning must not be NULL");
   for (size_t i = 0; i < plan->arrays.size(); ++i) {
-    tuning[3 * i] = plan->arrays[i].tune_transform;
-    tuning[3 * i + 1] = plan->arrays[i].tune_splits;
-    tuning[3 * i + 2] = int32_t(std::min(plan->arrays[i].tune_us, 2e9));
+    tuning[4 * i] = plan->arrays[i].tune_transform;
+    tuning[4 * i + 1] = plan->arrays[i].tune_splits;
+    tuning[4 * i + 2] = plan->arrays[i].tune_batch;
+    tuning[4 * i + 3] = int32_t(std::min(plan->arrays[i].tune_us, 2e9));
   }
   return EPIC_OK;
 }
@@ -1805,11 +1919,13 @@ int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning) {
 int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning) {
   if (!plan || !tuning) return fail(EPIC_ERR_ARG, "plan and tuning must not be NULL");
   for (size_t i = 0; i < plan->arrays.size(); ++i)
-    if (tuning[3 * i] < 0 || tuning[3 * i] > 4 || tuning[3 * i + 1] < 0)
+    if (tuning[4 * i] < 0 || tuning[4 * i] > 4 || tuning[4 * i + 1] < 0 ||
+        (tuning[4 * i + 2] != 0 && tuning[4 * i + 2] != 2 && tuning[4 * i + 2] != 4))
       return fail(EPIC_ERR_ARG, "bad tuning entry for array %zu", i);
   for (size_t i = 0; i < plan->arrays.size(); ++i) {
-    plan->arrays[i].tune_transform = tuning[3 * i];
-    plan->arrays[i].tune_splits = tuning[3 * i + 1];
+    plan->arrays[i].tune_transform = tuning[4 * i];
+    plan->arrays[i].tune_splits = tuning[4 * i + 1];
+    plan->arrays[i].tune_batch = tuning[4 * i + 2] == 2 ? 0 : tuning[4 * i + 2];
   }
   plan->generation++;
   return EPIC_OK;

@@ -49,6 +49,8 @@ struct ImageArgs {
   int dft_prec = 0;
   const uint2* slots_c = nullptr;
   int n_slots_c = 0;
+  // dense residue-class engine: gridding slots per batch (2 or 4; 0 = 2)
+  int grid_batch = 0;
 };
 
 // Stage-wise gridding to HBM.

@@ -365,7 +365,6 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
 // (padding slots: weight 0, first and not last, never stored).
 // ---------------------------------------------------------------------------
 constexpr int kClsDenseThreads = 512;
-constexpr int kClsDenseGridBatch = 2;
 
 template <int R>
 struct ClsDenseSmem {
@@ -455,7 +454,8 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
   }
 }
 
-template <int R, int FMT>
+// GB: gridding slots per batch (2 or 4, an autotuner choice).
+template <int R, int FMT, int GB>
 __device__ __forceinline__ void image_cls_dense_item(const ImageArgs& a, int f, int cg, int s, uint8_t* smem) {
   static_assert(FMT == kCI4 || FMT == kCI8, "integer E-field formats");
   using L = ClsDenseSmem<R>;
@@ -509,11 +509,11 @@ __device__ __forceinline__ void image_cls_dense_item(const ImageArgs& a, int f, 
                                       : make_float2(0.f, 0.f);
     });
     __syncthreads();                 // E' staged (and every half frame clear)
-    grid_dense_half<R, kClsDenseGridBatch>(H0, epr, tw, a.slots_m, S0, 0, cy0, owner);
+    grid_dense_half<R, GB>(H0, epr, tw, a.slots_m, S0, 0, cy0, owner);
     __syncthreads();                 // every class's first half gridded
     take_half_row<0>(v, H, lam);
     __syncthreads();                 // every half frame read and cleared
-    grid_dense_half<R, kClsDenseGridBatch>(H0, epr, tw, a.slots_m + S0 * OW, S1, 1, cy0, owner);
+    grid_dense_half<R, GB>(H0, epr, tw, a.slots_m + S0 * OW, S1, 1, cy0, owner);
     __syncthreads();                 // second halves gridded; E' free for the next step
     take_half_row<32>(v, H, lam);
     fft_reg<64, +1>(v);

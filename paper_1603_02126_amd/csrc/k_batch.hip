@@ -71,17 +71,17 @@ __device__ __noinline__ void cls_pair_call(const ImageArgs& a, int4 w, uint8_t* 
   const ImageArgs la = uniform_args(a, w);
   image_cls_pair_item<R, FMT, DB>(la, w.y, w.z, w.w, smem);
 }
-template <int R, int FMT>
+template <int R, int FMT, int GB>
 __device__ __noinline__ void dense_call(const ImageArgs& a, int4 w, uint8_t* smem) {
   const ImageArgs la = uniform_args(a, w);
-  image_cls_dense_item<R, FMT>(la, w.y, w.z, w.w, smem);
+  image_cls_dense_item<R, FMT, GB>(la, w.y, w.z, w.w, smem);
 }
 
 // Body codes: 1000 kind + parameters (0: no body, the array has its own launch).
 constexpr int fft8_code(int N, int apl) { return 1000 + 10 * N + apl; }
 constexpr int pair_code(int apl, int fmt) { return 2000 + 10 * apl + fmt; }
 constexpr int cls_pair_code(int R, int fmt, bool db) { return 3000 + 100 * R + 10 * fmt + (db ? 1 : 0); }
-constexpr int dense_code(int R, int fmt) { return 4000 + 100 * R + 10 * fmt; }
+constexpr int dense_code(int R, int fmt, int gb) { return 4000 + 100 * R + 10 * fmt + gb; }
 
 static_assert(FftSmem<32, 4, 8>::BYTES <= kLdsBytes && FftSmem<16, 8, 8>::BYTES <= kLdsBytes &&
                   PairSmem<4>::BYTES <= kLdsBytes && ClsPairSmem<4>::BYTES <= kLdsBytes &&
@@ -107,10 +107,14 @@ __device__ __forceinline__ void run_item(const ImageArgs& a, int code, int4 w, u
     case cls_pair_code(4, kCI4, false): cls_pair_call<4, kCI4, false>(a, w, smem); break;
     case cls_pair_code(4, kCI8, true): cls_pair_call<4, kCI8, true>(a, w, smem); break;
     case cls_pair_code(4, kCI4, true): cls_pair_call<4, kCI4, true>(a, w, smem); break;
-    case dense_code(2, kCI8): dense_call<2, kCI8>(a, w, smem); break;
-    case dense_code(2, kCI4): dense_call<2, kCI4>(a, w, smem); break;
-    case dense_code(4, kCI8): dense_call<4, kCI8>(a, w, smem); break;
-    case dense_code(4, kCI4): dense_call<4, kCI4>(a, w, smem); break;
+    case dense_code(2, kCI8, 2): dense_call<2, kCI8, 2>(a, w, smem); break;
+    case dense_code(2, kCI4, 2): dense_call<2, kCI4, 2>(a, w, smem); break;
+    case dense_code(4, kCI8, 2): dense_call<4, kCI8, 2>(a, w, smem); break;
+    case dense_code(4, kCI4, 2): dense_call<4, kCI4, 2>(a, w, smem); break;
+    case dense_code(2, kCI8, 4): dense_call<2, kCI8, 4>(a, w, smem); break;
+    case dense_code(2, kCI4, 4): dense_call<2, kCI4, 4>(a, w, smem); break;
+    case dense_code(4, kCI8, 4): dense_call<4, kCI8, 4>(a, w, smem); break;
+    case dense_code(4, kCI4, 4): dense_call<4, kCI4, 4>(a, w, smem); break;
     default: break;
   }
 }
@@ -154,7 +158,7 @@ int batch_body(const ImageArgs& a, int N, bool dft) {
   if ((N == 128 || N == 256) && integer) {
     const int R = N / 64;
     if (cls_pair_engine(a, N)) return cls_pair_code(R, a.fmt, cls_pair_db(a, N));
-    if (cls_dense_engine(a, N)) return dense_code(R, a.fmt);
+    if (cls_dense_engine(a, N)) return dense_code(R, a.fmt, a.grid_batch == 4 ? 4 : 2);
   }
   return 0;
 }

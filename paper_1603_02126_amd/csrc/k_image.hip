@@ -82,12 +82,12 @@ __global__ __launch_bounds__(kClsPairThreads) void k_image_cls_pair(ImageArgs a)
   image_cls_pair_item<R, FMT, DB>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
-template <int R, int FMT>
+template <int R, int FMT, int GB>
 __global__ __launch_bounds__(kClsDenseThreads) void k_image_cls_dense(ImageArgs a) {
   __shared__ __align__(16) uint8_t smem[ClsDenseSmem<R>::BYTES];
   constexpr int CG = (R * R) / ClsDenseSmem<R>::CPW;
   const int rest = blockIdx.x / a.F;
-  image_cls_dense_item<R, FMT>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
+  image_cls_dense_item<R, FMT, GB>(a, blockIdx.x % a.F, rest % CG, rest / CG, smem);
 }
 
 template <int R>
@@ -299,10 +299,17 @@ hipError_t launch_image(int N, const ImageArgs& a, hipStream_t s) {
     const dim3 grid(a.F * cls_groups(a, N) * a.splits);
     if (cls_dense_engine(a, N)) {
       const dim3 blk(kClsDenseThreads);
-      if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<2, kCI4>), grid, blk, 0, s, a);
-      else if (N == 128) hipLaunchKernelGGL((k_image_cls_dense<2, kCI8>), grid, blk, 0, s, a);
-      else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<4, kCI4>), grid, blk, 0, s, a);
-      else hipLaunchKernelGGL((k_image_cls_dense<4, kCI8>), grid, blk, 0, s, a);
+      if (a.grid_batch == 4) {
+        if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<2, kCI4, 4>), grid, blk, 0, s, a);
+        else if (N == 128) hipLaunchKernelGGL((k_image_cls_dense<2, kCI8, 4>), grid, blk, 0, s, a);
+        else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<4, kCI4, 4>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_image_cls_dense<4, kCI8, 4>), grid, blk, 0, s, a);
+      } else {
+        if (N == 128 && a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<2, kCI4, 2>), grid, blk, 0, s, a);
+        else if (N == 128) hipLaunchKernelGGL((k_image_cls_dense<2, kCI8, 2>), grid, blk, 0, s, a);
+        else if (a.fmt == kCI4) hipLaunchKernelGGL((k_image_cls_dense<4, kCI4, 2>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_image_cls_dense<4, kCI8, 2>), grid, blk, 0, s, a);
+      }
       return hipGetLastError();
     }
     if (cls_pair_engine(a, N)) {

@@ -94,6 +94,8 @@ _SIGS = {
     "epic_image_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "epic_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "epic_plan_autotune_cached": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_char_p,
+                                                 ctypes.c_void_p]),
     "epic_plan_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "epic_plan_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -346,23 +348,30 @@ class Plan:
         _check(load().epic_plan_get_timing(self._h, ms.ctypes.data, n.ctypes.data, TIMER_COUNT))
         return {k: (float(ms[k]), int(n[k])) for k in range(TIMER_COUNT)}
 
-    def autotune(self, efields, n_samples, stream=None):
-        """Time the candidate transforms / splits per array on these inputs and keep the fastest."""
+    def autotune(self, efields, n_samples, cache=None, stream=None):
+        """Time the candidate transforms / splits / gridding batches per array on
+        these inputs and keep the fastest; with `cache` (a JSON file path) arrays
+        already in the cache take its entry (epic_plan_autotune_cached)."""
         ptrs = [self._efield(i, efields[i], f"efield[{i}]")[0] for i in range(len(self.specs))]
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
-        _check(load().epic_plan_autotune(self._h, arr, int(n_samples), _stream(stream)))
+        if cache is None:
+            _check(load().epic_plan_autotune(self._h, arr, int(n_samples), _stream(stream)))
+        else:
+            _check(load().epic_plan_autotune_cached(self._h, arr, int(n_samples), os.fsencode(cache),
+                                                     _stream(stream)))
         return self.get_tuning()
 
     def get_tuning(self):
-        """[(transform, splits, imaging microseconds)] per array."""
-        t = np.zeros(3 * len(self.specs), np.int32)
+        """[(transform, splits, gridding batch, imaging microseconds)] per array."""
+        t = np.zeros(4 * len(self.specs), np.int32)
         _check(load().epic_plan_get_tuning(self._h, t.ctypes.data))
-        return [tuple(int(v) for v in t[3 * i:3 * i + 3]) for i in range(len(self.specs))]
+        return [tuple(int(v) for v in t[4 * i:4 * i + 4]) for i in range(len(self.specs))]
 
     def set_tuning(self, tuning):
-        t = np.zeros(3 * len(self.specs), np.int32)
-        for i, (tr, sp, *_) in enumerate(tuning):
-            t[3 * i], t[3 * i + 1] = tr, sp
+        t = np.zeros(4 * len(self.specs), np.int32)
+        for i, (tr, sp, *rest) in enumerate(tuning):
+            t[4 * i], t[4 * i + 1] = tr, sp
+            t[4 * i + 2] = rest[0] if rest else 0
         _check(load().epic_plan_set_tuning(self._h, t.ctypes.data))
 
     def _dims(self, i):

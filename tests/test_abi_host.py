@@ -19,7 +19,7 @@ def test_library_exports_every_header_function():
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert set(names) == set(lib._SIGS), set(names) ^ set(lib._SIGS)
-    assert L.epic_abi_version() == 1
+    assert L.epic_abi_version() == 2
 
 
 @pytest.mark.parametrize("cfg", ["tiny", "small", "lwa", "hera"])

@@ -103,7 +103,7 @@ def test_autotune_then_run_matches_oracle(cuda):
     plan = _plan(wls)
     es = [torch.from_numpy(p).to(cuda) for p in packs]
     tuning = plan.autotune(es, wls[0].n_samples)
-    assert len(tuning) == len(wls) and all(t[0] in (1, 2) and t[1] >= 1 for t in tuning)
+    assert len(tuning) == len(wls) and all(t[0] in (1, 2, 3, 4) and t[1] >= 1 and t[2] in (0, 4) for t in tuning)
     (gs, imgs), = _run(plan, wls, packs, cuda)
     for w, p, g, img in zip(wls, packs, gs, imgs):
         ref = oracle_run(w, p)
@@ -144,3 +144,29 @@ def test_graph_follows_option_changes_and_new_inputs(cuda):
             assert gain_err(g.cpu().numpy(), ref["gains"][-1]) <= GAIN_RTOL, (opts, w.name)
             assert image_err(img.cpu().numpy(), ref["image"]).max() <= IMAGE_RTOL, (opts, w.name)
     plan.close()
+
+
+def test_autotune_cache_round_trip(cuda, tmp_path):
+    """The tuning cache: a first autotune writes one entry per array, a
+    second plan takes them without timing (same choices), and a run with the
+    cached tuning matches the FP64 oracle."""
+    import json
+    import torch
+    wls = _small_uneven(n_chan=2, n_samples=60)
+    packs = [synth.make_efield(w) for w in wls]
+    es = [torch.from_numpy(p).to(cuda) for p in packs]
+    path = str(tmp_path / "tune.json")
+    a = _plan(wls)
+    ta = a.autotune(es, 60, cache=path)
+    a.close()
+    entries = json.load(open(path))
+    assert len(entries) == len(wls) and all("|N=" in k for k in entries)
+    b = _plan(wls)
+    tb = b.autotune(es, 60, cache=path)
+    assert [t[:3] for t in tb] == [t[:3] for t in ta]
+    (gs, imgs), = _run(b, wls, packs, cuda)
+    for w, p, g, img in zip(wls, packs, gs, imgs):
+        ref = oracle_run(w, p)
+        assert gain_err(g, ref["gains"][-1]) <= GAIN_RTOL, w.name
+        assert image_err(img, ref["image"]).max() <= IMAGE_RTOL, w.name
+    b.close()

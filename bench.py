@@ -51,8 +51,8 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "ff4512de27187ac0625eda944ca909dba1c72e2ac59ddb3677c28b22fd33d35b",
-            "fetch_kib": 175060.2, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "09a112be0d8c5e9e7a88443c27a79c25dfdb65bb5c48108b82154bd4ba7d4ed5",
+            "fetch_kib": 175059.0, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
     "lwa_snapshot1": {"sources_sha256": "ff4512de27187ac0625eda944ca909dba1c72e2ac59ddb3677c28b22fd33d35b",
                       "fetch_kib": 174337.4, "fetch_scale": 2.000, "write_kib": 20488238.8, "write_scale": 1.000},
 }
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "ff4512de27187ac0625eda944ca909dba1c72e2ac59ddb3677c28b22fd33d35b", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "09a112be0d8c5e9e7a88443c27a79c25dfdb65bb5c48108b82154bd4ba7d4ed5", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
 }
 
 

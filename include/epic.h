@@ -278,8 +278,10 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 /* Autotuner: for every array, time the imaging launch of the given E-field
  * stream (n_samples samples) with each candidate transform (FFT; for the grids
  * and arrays the DFT-GEMM covers, its three precisions), time-split count
- * (frames per workgroup) and, for the dense residue-class engine, gridding
- * batch (2 or 4 slots), and keep the fastest for later runs.
+ * (frames per workgroup) and, at 128 x 128 and 256 x 256 with integer
+ * samples, residue-class engine (the default, and the dense engine with
+ * gridding batches of 2 and 4 schedule entries), and keep the fastest for
+ * later runs.
  * Synchronous (waits for the device); efield: one device pointer per array. */
 int epic_plan_autotune(epic_plan_t plan, const void* const* efield, int64_t n_samples,
                        epic_stream_t stream);
@@ -296,7 +298,11 @@ int epic_plan_autotune_cached(epic_plan_t plan, const void* const* efield, int64
 
 /* Tuning state per array: tuning[4 i + 0] = transform (EPIC_OPT_TRANSFORM
  * values 1..4, 0 = plan default), [4 i + 1] = time splits (0 = auto),
- * [4 i + 2] = dense class engine gridding batch (0 or 2 = default, 4),
+ * [4 i + 2] = residue-class engine (grids 128 and 256, integer samples):
+ * 0 = default (the class-pair engine up to 512 antennas where its tables
+ * fit, else the dense engine gridding 2 schedule entries per batch), 2 or 4 =
+ * the dense engine with batches of 2 or 4 entries (ignored where it does not
+ * apply: cf32 samples, other grids, more antennas than it stages),
  * [4 i + 3] = measured imaging time in microseconds (get only).  Host arrays
  * of 4 * n_arrays. */
 int epic_plan_get_tuning(epic_plan_t plan, int32_t* tuning);

@@ -71,5 +71,52 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+ASAN_CHECK = os.path.join(ROOT, "tests", "host_asan", "epic_asan_check.cpp")
+
+
+def build_asan_check(out_dir: str, device: bool = True, verbose: bool = False) -> str:
+    """Build the host-side AddressSanitizer + UndefinedBehaviorSanitizer check
+    (tests/host_asan/epic_asan_check.cpp) against freshly compiled library
+    objects.  Only the host side of every source is instrumented; device code
+    is compiled as usual (device=False compiles the host side alone, for
+    machines without a GPU).  Returns the executable's path."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+    mode = [] if device else ["--offload-host-only"]
+
+    def comp(src):
+        obj = os.path.join(out_dir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmd = [hipcc(), *common_flags(), *mode, *san, "-O1", "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [ASAN_CHECK]
+    with ThreadPoolExecutor(len(srcs)) as ex:
+        objs = list(ex.map(comp, srcs))
+    exe = os.path.join(out_dir, "epic_asan_check")
+    # the sanitizer runtimes are linked by the host compiler on a line of its own
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang++"
+    rocm = os.path.realpath(os.path.join(os.path.dirname(os.path.realpath(hipcc())), ".."))
+    cmd = [clang, "-fsanitize=address,undefined", *objs, "-o", exe, "-L", os.path.join(rocm, "lib"),
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lamdhip64"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--asan-check" in sys.argv:
+        out = sys.argv[sys.argv.index("--asan-check") + 1]
+        print(build_asan_check(out, device="--host-only" not in sys.argv, verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

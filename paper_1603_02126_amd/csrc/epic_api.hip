@@ -1714,7 +1714,7 @@ int epic_image_adjoint(epic_plan_t plan, int32_t array, const void* efield, int6
 }
 
 // Time the candidate imaging launches of array i and keep the fastest
-// (transform, time splits, dense gridding batch).
+// (transform, time splits, residue-class engine and its gridding batch).
 static int autotune_array(epic_plan_t plan, int i, const void* efield, int64_t n_samples, hipStream_t s) {
   ArrayPlan& ap = plan->arrays[i];
   int rc = check_grid_supported(ap);
@@ -1753,10 +1753,20 @@ static int autotune_array(epic_plan_t plan, int i, const void* efield, int64_t n
   for (int tr : trs)
     for (int sp : sps) {
       ap.tune_transform = tr;
-      ap.tune_batch = 0;
-      // the dense class engine's gridding batch (other engines size theirs from the schedule)
+      // the residue-class engine: the default, and the dense engine with each
+      // gridding batch where it applies (0 and 2 are one candidate where the
+      // dense engine is the default)
       std::vector<int> gbs{0};
-      if (!uses_dft(plan, ap) && epic::cls_dense_engine(engine_probe(ap), h.nx)) gbs.push_back(4);
+      if (!uses_dft(plan, ap)) {
+        ap.tune_batch = 0;
+        const bool pair_default = epic::cls_pair_engine(engine_probe(ap), h.nx);
+        ap.tune_batch = 2;
+        if (epic::cls_dense_engine(engine_probe(ap), h.nx)) {
+          if (pair_default) gbs.push_back(2);
+          gbs.push_back(4);
+        }
+      }
+      ap.tune_batch = 0;
       for (int gb : gbs) {
         ap.tune_batch = gb;
         ap.tune_splits = sp;
@@ -1925,7 +1935,7 @@ int epic_plan_set_tuning(epic_plan_t plan, const int32_t* tuning) {
   for (size_t i = 0; i < plan->arrays.size(); ++i) {
     plan->arrays[i].tune_transform = tuning[4 * i];
     plan->arrays[i].tune_splits = tuning[4 * i + 1];
-    plan->arrays[i].tune_batch = tuning[4 * i + 2] == 2 ? 0 : tuning[4 * i + 2];
+    plan->arrays[i].tune_batch = tuning[4 * i + 2];
   }
   plan->generation++;
   return EPIC_OK;

@@ -49,7 +49,9 @@ struct ImageArgs {
   int dft_prec = 0;
   const uint2* slots_c = nullptr;
   int n_slots_c = 0;
-  // dense residue-class engine: gridding slots per batch (2 or 4; 0 = 2)
+  // residue-class engine choice at 128 / 256 with integer samples: 0 = the
+  // default (class-pair engine where it applies, else the dense engine with
+  // gridding batches of 2); 2 or 4 = the dense engine with that batch
   int grid_batch = 0;
 };
 

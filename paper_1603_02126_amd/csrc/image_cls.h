@@ -119,9 +119,9 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
           const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
           const float w = __uint_as_float(e[j].y);
           const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
-          const bool first = int(code) < 0;
-          sum.x = first ? ev.x : sum.x + ev.x;
-          sum.y = first ? ev.y : sum.y + ev.y;
+          const float keep = int(code) < 0 ? 0.f : 1.f;   // a cell's first contribution restarts the sum
+          sum.x = fmaf(sum.x, keep, ev.x);
+          sum.y = fmaf(sum.y, keep, ev.y);
           const int off = (code >> 30) & 1 ? qy * P + qx : 64;
           if (k0 + j < S) buf[off] = sum;
         });
@@ -136,9 +136,9 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
         const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
         const float w = __uint_as_float(e.y);
         const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
-        const bool first = int(code) < 0;
-        sum.x = first ? ev.x : sum.x + ev.x;
-        sum.y = first ? ev.y : sum.y + ev.y;
+        const float keep = int(code) < 0 ? 0.f : 1.f;
+        sum.x = fmaf(sum.x, keep, ev.x);
+        sum.y = fmaf(sum.y, keep, ev.y);
         const int off = (code >> 30) & 1 ? qy * P + qx : 64;
         buf[off] = sum;
       }
@@ -219,9 +219,9 @@ __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, cons
       const uint32_t code = e[k].x;
       const float w = __uint_as_float(e[k].y);
       const float2 c = cmul(ev[k], make_float2(w * ph[k].x, w * ph[k].y));
-      const bool first = int(code) < 0;
-      sum.x = first ? c.x : sum.x + c.x;
-      sum.y = first ? c.y : sum.y + c.y;
+      const float keep = int(code) < 0 ? 0.f : 1.f;   // a cell's first contribution restarts the sum
+      sum.x = fmaf(sum.x, keep, c.x);
+      sum.y = fmaf(sum.y, keep, c.y);
       const int qx = (code >> 12) & 63, qy = (code >> 18) & 63;
       const int off = (code >> 30) & 1 ? qy * kHalfPitch + qx - 32 * hf : 32;
       if (s0 + k < S) H[off] = sum;
@@ -428,7 +428,10 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
       });
       const float w = __uint_as_float(e[k].y);
       const float2 z = make_float2(w * ev.x, w * ev.y);
-      const bool first = int(code) < 0, last = (code >> 30) & 1;
+      // a cell's first contribution restarts its sums: acc * 0 + c, one FMA
+      // per component instead of an add and a select
+      const float keep = int(code) < 0 ? 0.f : 1.f;
+      const bool last = (code >> 30) & 1;
       static_for<0, NCY>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         const float2 zy = cmul(z, ty[j]);
@@ -437,8 +440,8 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
           float2 c;
           if constexpr (m == 0) c = zy;
           else c = cmul(zy, tx[m]);
-          acc[j][m].x = first ? c.x : acc[j][m].x + c.x;
-          acc[j][m].y = first ? c.y : acc[j][m].y + c.y;
+          acc[j][m].x = fmaf(acc[j][m].x, keep, c.x);
+          acc[j][m].y = fmaf(acc[j][m].y, keep, c.y);
         });
       });
       if (last && s0 + k < S) {

@@ -451,9 +451,9 @@ __device__ __forceinline__ void dft_cls_item(const ImageArgs& a, int f, int cp, 
         const float2 ph = tw[(jx * cx + jy * cy) & (N - 1)];
         const float w = __uint_as_float(e.y);
         const float2 ev = cmul(epr[code & kSlotAntMask], make_float2(w * ph.x, w * ph.y));
-        const bool first = int(code) < 0;
-        sum.x = first ? ev.x : sum.x + ev.x;
-        sum.y = first ? ev.y : sum.y + ev.y;
+        const float keep = int(code) < 0 ? 0.f : 1.f;   // a cell's first contribution restarts the sum
+        sum.x = fmaf(sum.x, keep, ev.x);
+        sum.y = fmaf(sum.y, keep, ev.y);
         if ((code >> 30) & 1) {
           gt[qx * P + qy] = sum;
           mx = fmaxf(mx, fmaxf(fabsf(sum.x), fabsf(sum.y)));

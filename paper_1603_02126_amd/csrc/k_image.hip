@@ -275,14 +275,16 @@ bool cls_pair_db(const ImageArgs& a, int N) {
 }
 
 bool cls_pair_engine(const ImageArgs& a, int N) {
-  if (!(N == 128 || N == 256) || a.fmt == kCF32 || a.Na > kClsMaxAnt || !a.slots_h) return false;
+  if (!(N == 128 || N == 256) || a.fmt == kCF32 || a.Na > kClsMaxAnt || !a.slots_h || a.grid_batch != 0)
+    return false;
   const int cap = N == 128 ? ClsPairSmem<2>::TAB_SLOTS : ClsPairSmem<4>::TAB_SLOTS;
   return a.n_slots_h0 + a.n_slots_h1 <= cap;
 }
 
 // The dense residue-class engine with two waves per SIMD: integer E-fields,
-// arrays the class-pair engine does not take, up to 2048 antennas at
-// 256 x 256 and 1024 at 128 x 128 (its E' staging of one or two frames).
+// up to 2048 antennas at 256 x 256 and 1024 at 128 x 128 (its E' staging of
+// one or two frames); by default the arrays the class-pair engine does not
+// take, any of them when a gridding batch is chosen (grid_batch 2 or 4).
 bool cls_dense_engine(const ImageArgs& a, int N) {
   if (!(N == 128 || N == 256) || a.fmt == kCF32 || !a.slots_m || cls_pair_engine(a, N)) return false;
   return a.Na <= (N == 256 ? ClsDenseSmem<4>::MAXA : ClsDenseSmem<2>::MAXA);

@@ -349,7 +349,7 @@ class Plan:
         return {k: (float(ms[k]), int(n[k])) for k in range(TIMER_COUNT)}
 
     def autotune(self, efields, n_samples, cache=None, stream=None):
-        """Time the candidate transforms / splits / gridding batches per array on
+        """Time the candidate transforms / splits / class engines per array on
         these inputs and keep the fastest; with `cache` (a JSON file path) arrays
         already in the cache take its entry (epic_plan_autotune_cached)."""
         ptrs = [self._efield(i, efields[i], f"efield[{i}]")[0] for i in range(len(self.specs))]
@@ -362,7 +362,9 @@ class Plan:
         return self.get_tuning()
 
     def get_tuning(self):
-        """[(transform, splits, gridding batch, imaging microseconds)] per array."""
+        """[(transform, splits, class engine, imaging microseconds)] per array;
+        class engine 0 = default, 2 or 4 = the dense residue-class engine with
+        gridding batches of that many schedule entries."""
         t = np.zeros(4 * len(self.specs), np.int32)
         _check(load().epic_plan_get_tuning(self._h, t.ctypes.data))
         return [tuple(int(v) for v in t[4 * i:4 * i + 4]) for i in range(len(self.specs))]

@@ -39,7 +39,7 @@ def oracle_run(wl, packed, channels=None):
     return O.run(E, pb, wl.g0, channels=chans)
 
 
-def gpu_run(wl, packed, device, plan=None, splits=0, hist=True, transform=0):
+def gpu_run(wl, packed, device, plan=None, splits=0, hist=True, transform=0, cls_engine=0):
     import torch
     from paper_1603_02126_amd import lib
     own = plan is None
@@ -50,6 +50,8 @@ def gpu_run(wl, packed, device, plan=None, splits=0, hist=True, transform=0):
         plan.set_option(lib.OPT_SPLITS, splits)
     if transform:
         plan.set_option(lib.OPT_TRANSFORM, transform)
+    if cls_engine:
+        plan.set_tuning([(0, 0, cls_engine)])
     a = wl.array
     e = torch.from_numpy(np.ascontiguousarray(packed)).to(device)
     g = torch.from_numpy(np.ascontiguousarray(wl.g0)).to(device)

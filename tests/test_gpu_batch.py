@@ -103,7 +103,7 @@ def test_autotune_then_run_matches_oracle(cuda):
     plan = _plan(wls)
     es = [torch.from_numpy(p).to(cuda) for p in packs]
     tuning = plan.autotune(es, wls[0].n_samples)
-    assert len(tuning) == len(wls) and all(t[0] in (1, 2, 3, 4) and t[1] >= 1 and t[2] in (0, 4) for t in tuning)
+    assert len(tuning) == len(wls) and all(t[0] in (1, 2, 3, 4) and t[1] >= 1 and t[2] in (0, 2, 4) for t in tuning)
     (gs, imgs), = _run(plan, wls, packs, cuda)
     for w, p, g, img in zip(wls, packs, gs, imgs):
         ref = oracle_run(w, p)

@@ -186,15 +186,19 @@ def test_run_maximum_antennas(cuda, n, efmt, kernel, na, n_samples, t_cal):
     (256, synth.FMT_CI4, 1500, 29, 8),
     (128, synth.FMT_CI8, 1000, 41, 20),      # two frames per step, odd sample count
     (128, synth.FMT_CI4, 700, 8, 3),
+    (128, synth.FMT_CI8, 350, 23, 10),       # class-pair arrays, dense engine chosen
+    (256, synth.FMT_CI4, 60, 19, 7),
 ])
-def test_dense_class_engine(cuda, n, efmt, na, n_samples, t_cal):
+@pytest.mark.parametrize("batch", [0, 4])
+def test_dense_class_engine(cuda, n, efmt, na, n_samples, t_cal, batch):
     """The dense residue-class engine with two waves per SIMD (513..2048
-    antennas at 256 x 256, up to 1024 at 128 x 128; slot tables read from
-    memory in batches)."""
+    antennas at 256 x 256, up to 1024 at 128 x 128 by default; any integer
+    array when chosen), gridding 2 or 4 schedule entries per batch from slot
+    tables read from memory."""
     wl = synth.config_small(n=n, efmt=efmt, kernel=2, n_ant=na, n_chan=2, n_samples=n_samples, t_cal=t_cal)
     packed = synth.make_efield(wl)
     ref = oracle_run(wl, packed)
-    got = gpu_run(wl, packed, cuda)
+    got = gpu_run(wl, packed, cuda, cls_engine=batch if na > 512 else (batch or 2))
     assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
 

@@ -100,6 +100,38 @@ __device__ __forceinline__ double row16_sum_lane15(double x) {
   return x;
 }
 
+// Two's complement nibbles / bytes of one packed integer sample -> int (exact).
+__device__ __forceinline__ int2 unpack_int(Raw r, int fmt) {
+  if (fmt == kCI4) {
+    const int b = int(int8_t(uint8_t(r.x)));
+    return make_int2(b >> 4, int(int8_t(uint8_t(r.x << 4))) >> 4);
+  }
+  return make_int2(int(int8_t(uint8_t(r.x))), int(int8_t(uint8_t(r.x >> 8))));
+}
+
+// The damped update of eq. (damping) with the two per-antenna constants
+// folded in: r = 1 / (Na |g|^2) of this interval's gain (the same factor
+// makes c = A conj(g) r) and invD = Na conj(D) / |D|^2, fixed for the run.
+//   C = K - conj(A) Q / (Na conj g) = K - conj(A) g (Q r)     (eq. Cna)
+//   g' = (1 - gamma) C invD + gamma g                          (eq. cal_solution)
+// One real division per antenna and interval instead of six.
+__device__ __forceinline__ double2 epical_step_r(double2 Kbar, double Qbar, double2 A, double2 invD, double2 g,
+                                                 double r, uint8_t hold, double gamma, uint32_t* st) {
+  if (hold) {
+    *st |= (hold & kHoldFlagged ? 1u : 0u) | (hold & kHoldDZero ? 2u : 0u);
+    return g;
+  }
+  const double qr = Qbar * r;
+  const double2 t = zmul(zconj(A), make_double2(g.x * qr, g.y * qr));
+  const double2 sol = zmul(make_double2(Kbar.x - t.x, Kbar.y - t.y), invD);
+  const double2 gn = make_double2((1.0 - gamma) * sol.x + gamma * g.x, (1.0 - gamma) * sol.y + gamma * g.y);
+  if (!isfinite(gn.x) || !isfinite(gn.y)) {
+    *st |= 4u;
+    return g;
+  }
+  return gn;
+}
+
 // J = antennas per thread slot (Na <= 1024 * J), PS = chunk piece size.
 // LDS of one solve workgroup: two chunk buffers, the taps of a chunk and the
 // coefficients c_a (up to 2 * kSolveThreads antennas), both FP64.
@@ -134,20 +166,24 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
   const int rg = tid % RG;
   const int a0 = tid / RG;
 
-  double2 g[J], A[J], D[J];   // D is loaded once: the per-interval update must not wait on memory
+  // invD = Na conj(D) / |D|^2 is loaded and formed once: the per-interval
+  // update must not wait on memory or on a division by D
+  double2 g[J], A[J], invD[J];
   uint8_t hold[J];
   uint32_t st[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int an = a0 + NaP * j;
-    g[j] = A[j] = D[j] = make_double2(0.0, 0.0);
+    g[j] = A[j] = invD[j] = make_double2(0.0, 0.0);
     hold[j] = 0;
     st[j] = 0u;
     if (an < a.Na) {
       const int64_t ia = int64_t(f) * a.Na + an;
       g[j] = a.gains[ia];
       A[j] = a.A[ia];
-      D[j] = a.D[ia];
+      const double2 D = a.D[ia];
+      const double d2 = D.x * D.x + D.y * D.y;
+      invD[j] = make_double2(a.na_eff * D.x / d2, -a.na_eff * D.y / d2);
       hold[j] = a.hold[ia];
       if (rg == 0) a.g_hist[ia] = g[j];
     }
@@ -170,16 +206,18 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
   for (int n = 0; n < a.n_int; ++n) {
     const int64_t t0 = int64_t(n) * a.t_cal;
     const int len = interval_len(n);
-    // c_a = A_a u_a / Na, u_a = 1 / g_a (zero for flagged antennas)
+    // c_a = A_a u_a / Na = A_a conj(g_a) r_a, u_a = 1 / g_a (zero for flagged antennas)
+    double rr[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) rr[j] = 1.0 / (a.na_eff * (g[j].x * g[j].x + g[j].y * g[j].y));
     if (rg == 0) {
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const int an = a0 + NaP * j;
         if (an < a.Na) {
-          double2 u = zrecip(g[j]);
-          if (hold[j] & kHoldFlagged) u = make_double2(0.0, 0.0);
-          const double2 c = zmul(A[j], u);
-          c_l[an] = make_double2(c.x / a.na_eff, c.y / a.na_eff);
+          double2 c = zmul(A[j], make_double2(g[j].x * rr[j], -g[j].y * rr[j]));
+          if (hold[j] & kHoldFlagged) c = make_double2(0.0, 0.0);
+          c_l[an] = c;
         }
       }
     }
@@ -211,10 +249,19 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
             const uint8_t* row = ch + r * RB;
 #pragma unroll 4
             for (int an = q; an < a.Na; an += 16) {
-              const float2 e = load_sample(row, an, FMT);
+              double ex, ey;
+              if constexpr (FMT == kCF32) {
+                const float2 e = load_sample(row, an, FMT);
+                ex = e.x;
+                ey = e.y;
+              } else {
+                const int2 e = unpack_int(load_raw(row, an, FMT), FMT);
+                ex = e.x;
+                ey = e.y;
+              }
               const double2 c = c_l[an];
-              px = fma(c.x, double(e.x), fma(-c.y, double(e.y), px));
-              py = fma(c.x, double(e.y), fma(c.y, double(e.x), py));
+              px = fma(c.x, ex, fma(-c.y, ey, px));
+              py = fma(c.x, ey, fma(c.y, ex, py));
             }
           }
           px = row16_sum_lane15(px);
@@ -228,19 +275,36 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
       for (int j = 0; j < J; ++j) {
         const int an = a0 + NaP * j;
         if (an < a.Na) {
-          double kx = 0.0, ky = 0.0, q = 0.0;
+          double kx = 0.0, ky = 0.0;
+          if constexpr (FMT == kCF32) {
+            double q = 0.0;
 #pragma unroll 4
-          for (int r = rg; r < nr; r += RG) {
-            const float2 e = load_sample(ch + r * RB, an, FMT);
-            const double ex = e.x, ey = e.y;
-            const double2 p = P_l[r];
-            kx = fma(ex, p.x, fma(ey, p.y, kx));
-            ky = fma(ey, p.x, fma(-ex, p.y, ky));
-            q = fma(ex, ex, fma(ey, ey, q));
+            for (int r = rg; r < nr; r += RG) {
+              const float2 e = load_sample(ch + r * RB, an, FMT);
+              const double ex = e.x, ey = e.y;
+              const double2 p = P_l[r];
+              kx = fma(ex, p.x, fma(ey, p.y, kx));
+              ky = fma(ey, p.x, fma(-ex, p.y, ky));
+              q = fma(ex, ex, fma(ey, ey, q));
+            }
+            Q[j] += q;
+          } else {
+            // |E|^2 of integer samples summed exactly in integers (at most
+            // 1024 rows of 2 * 128^2 per chunk)
+            int qi = 0;
+#pragma unroll 4
+            for (int r = rg; r < nr; r += RG) {
+              const int2 e = unpack_int(load_raw(ch + r * RB, an, FMT), FMT);
+              const double ex = e.x, ey = e.y;
+              const double2 p = P_l[r];
+              kx = fma(ex, p.x, fma(ey, p.y, kx));
+              ky = fma(ey, p.x, fma(-ex, p.y, ky));
+              qi += e.x * e.x + e.y * e.y;
+            }
+            Q[j] += double(qi);
           }
           Kx[j] += kx;
           Ky[j] += ky;
-          Q[j] += q;
         }
       }
       if (have_next) stg.store(chunk[cur_buf ^ 1], nr_nx, RB, tid);
@@ -262,8 +326,8 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
     for (int j = 0; j < J; ++j) {
       const int an = a0 + NaP * j;
       if (an < a.Na) {
-        const double2 gn = epical_step(make_double2(Kx[j] * inv_n, Ky[j] * inv_n), Q[j] * inv_n, A[j],
-                                       D[j], g[j], hold[j], a.na_eff, a.gamma, &st[j]);
+        const double2 gn = epical_step_r(make_double2(Kx[j] * inv_n, Ky[j] * inv_n), Q[j] * inv_n, A[j],
+                                         invD[j], g[j], rr[j], hold[j], a.gamma, &st[j]);
         g[j] = gn;
         if (rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = gn;
       }

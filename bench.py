@@ -453,6 +453,22 @@ def bench_single(args, dev):
     print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
     frames = a.n_chan * wl.n_samples
     forms = {}
+    # the fused run (one launch for solve and imaging, the default where the
+    # plan allows it) times as imaging only; the separate launches give each
+    # kernel's own duration, which the roofline and the kernel table use
+    fused = tim[lib.TIMER_SOLVE][1] == 0 and tim[lib.TIMER_IMAGE][1] > 0
+    tim_k, dt_sep = tim, None
+    if fused:
+        plan_s = new_plan([wl], {lib.OPT_OVERLAP: 0, **({lib.OPT_SPLITS: args.splits} if args.splits else {})},
+                          pix, band)
+        img_s = torch.zeros_like(img)
+        dt_sep, tim_k = Timer([plan_s])(stepper(plan_s, img_s), args.steps, args.warmup)
+        forms["separate_launches"] = {
+            "ms_per_step": dt_sep / args.steps * 1e3, "frames_per_s": frames / (dt_sep / args.steps),
+            "speedup_of_fused_run": dt_sep / dt,
+            "gains_equal_fused": bool(np.array_equal(g.cpu().numpy(), gains_plain)),
+            "max_rel_diff_vs_fused": rel_err(img_s.cpu().numpy(), img.cpu().numpy())}
+        plan_s.close()
     if not args.no_forms:
         for name, tr, prods in DFT_FORMS:
             if not (a.nx in (32, 64) or (a.nx in (128, 256) and a.n_ant <= 512)):
@@ -500,16 +516,20 @@ def bench_single(args, dev):
     ms_step = dt / args.steps * 1e3
     value = frames / (dt / args.steps)
     k2 = 1 if a.kernel == 1 else 4
-    img_ms, img_n = tim[lib.TIMER_IMAGE]
+    img_ms, img_n = tim_k[lib.TIMER_IMAGE]
     avg_img_ms = img_ms / max(1, img_n)
     flops_launch = imaging_flops_per_frame(a.nx, a.n_ant, k2) * frames
     achieved = flops_launch / (avg_img_ms * 1e-3) / 1e12
     bpe = synth.FMT_BYTES[a.efmt]
     bytes_launch = imaging_bytes_per_frame(a.n_ant, bpe, a.nx, wl.n_samples, wl.t_cal) * frames
     traffic = measured_traffic(args.workload) if not args.splits else None
-    kernels = {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
-               "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps),
-               "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)}
+    kernels = {"imaging": per_step(tim_k, lib.TIMER_IMAGE, args.steps),
+               "calibration_solve": per_step(tim_k, lib.TIMER_SOLVE, args.steps),
+               "image_reduce": per_step(tim_k, lib.TIMER_REDUCE, args.steps)}
+    if fused:
+        kernels = {"fused_solve_and_imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+                   "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps),
+                   "separate_launches": kernels}
 
     cpu, parity = None, None
     if args.cpu_budget > 0 and band is not None:
@@ -532,10 +552,14 @@ def bench_single(args, dev):
 
     engine = "k_image (calibrate+grid+FFT+|X|^2)" if a.nx <= 64 else \
         f"k_image_cls<{a.nx // 64}> (calibrate+grid by residue class+64-point FFTs+|X|^2)"
+    if fused:
+        engine += "; timed in the separate-launch form of the same plan"
+    path = ("FP32 FFT, fused solve + imaging launch (k_run_fused)" if fused
+            else "FP32 FFT, separate solve and imaging launches")
     out = base_record(args, value, ms_step, "f32", {
         "workload": describe(wl), "frames_per_step": frames, "n_ant": a.n_ant, "n_chan": a.n_chan,
         "grid": [a.ny, a.nx], "n_samples": wl.n_samples, "t_cal": wl.t_cal, "efmt": synth.FMT_NAMES[a.efmt],
-        "path": "plain FP32 FFT", "parallelism": "1 GPU", "tapped_pixels": args.pixels,
+        "path": path, "parallelism": "1 GPU", "tapped_pixels": args.pixels,
         "band": None if band is None else {"channels": [band[0], band[1]], "mode": "mean"}})
     out.update({
         "msamples_per_s": value * a.n_ant / 1e6,
@@ -547,7 +571,9 @@ def bench_single(args, dev):
                      "flops_per_frame": imaging_flops_per_frame(a.nx, a.n_ant, k2),
                      "hbm_bytes_per_frame": bytes_launch / frames,
                      "hbm_frac": bytes_launch / (avg_img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                     "sq_counters": measured_sq(args.workload) if not args.splits else None},
+                     "sq_counters": measured_sq(args.workload) if not args.splits else None,
+                     "fused_launch_ms": (tim[lib.TIMER_IMAGE][0] / max(1, tim[lib.TIMER_IMAGE][1])
+                                         if fused else None)},
         "kernels": kernels,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
@@ -670,7 +696,7 @@ def bench_uneven(args, dev):
             pl.run(es, T, gs, imgs)
         return step
 
-    plan = new_plan(wls, {lib.OPT_BATCH: 2})
+    plan = new_plan(wls)
     imgs = images()
     dt, tim = Timer([plan])(stepper(plan, imgs), args.steps, args.warmup)
     gains_plain = [g.cpu().numpy() for g in gs]
@@ -678,6 +704,20 @@ def bench_uneven(args, dev):
     frames = sum(w.array.n_chan for w in wls) * T
     flops_step = sum(imaging_flops_per_frame(w.array.nx, w.array.n_ant, 4) * w.array.n_chan * T for w in wls)
     forms = {}
+    # per-array separate launches (solve, imaging, reduction of each array):
+    # the imaging kernels' own durations for the roofline
+    fused = tim[lib.TIMER_SOLVE][1] == 0
+    tim_k, dt_k = tim, dt
+    if fused:
+        plan_s = new_plan(wls, {lib.OPT_BATCH: 2, lib.OPT_OVERLAP: 0})
+        imgs_s = images()
+        dt_k, tim_k = Timer([plan_s])(stepper(plan_s, imgs_s), args.steps, args.warmup)
+        forms["separate_per_array_launches"] = {
+            "ms_per_step": dt_k / args.steps * 1e3, "frames_per_s": frames / (dt_k / args.steps),
+            "speedup_of_fused_run": dt_k / dt,
+            "gains_equal_fused": all(np.array_equal(g.cpu().numpy(), gp) for g, gp in zip(gs, gains_plain)),
+            "max_rel_diff_vs_fused": max(rel_err(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(imgs_s, imgs))}
+        plan_s.close()
     if not args.no_forms:
         plan_g = new_plan(wls)
         tuning = plan_g.autotune(es, T)
@@ -697,7 +737,7 @@ def bench_uneven(args, dev):
         plan_g.close()
     if args.copy_calib:
         copy_reference(dev)
-    img_ms = tim[lib.TIMER_IMAGE][0] / args.steps
+    img_ms = tim_k[lib.TIMER_IMAGE][0] / args.steps
     achieved = flops_step / (img_ms * 1e-3) / 1e12
     bytes_step = sum(imaging_bytes_per_frame(w.array.n_ant, synth.FMT_BYTES[w.array.efmt], w.array.nx, T, w.t_cal)
                      * w.array.n_chan * T for w in wls)
@@ -736,19 +776,28 @@ def bench_uneven(args, dev):
         "workload": "uneven: 8 arrays, antennas " + ",".join(str(w.array.n_ant) for w in wls) + ", grids " +
                     ",".join(f"{w.array.nx}^2" for w in wls) + f", ci8, {wls[0].array.n_chan} channels each, "
                     f"{T} samples, gains every {wls[0].t_cal}",
-        "frames_per_step": frames, "path": "plain FP32 FFT, one launch per array per stage",
+        "frames_per_step": frames,
+        "path": ("FP32 FFT, one fused solve + imaging launch for all arrays (k_run_fused)" if fused
+                 else "FP32 FFT, one launch per array per stage"),
         "parallelism": "1 GPU"})
     out.update({
         "msamples_per_s": sum(w.array.n_ant * w.array.n_chan for w in wls) * T / (dt / args.steps) / 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel": "imaging kernels of all arrays (FFT, residue-class engines)",
+                     "kernel": "imaging kernels of all arrays (FFT, residue-class engines), timed as "
+                               "separate per-array launches",
                      "imaging_ms_per_step": img_ms,
                      "algorithmic_bytes_per_step": bytes_step,
                      "hbm_frac": bytes_step / (img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
-        "kernels": {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
-                    "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps),
-                    "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)},
+        "kernels": ({"fused_solve_and_imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+                     "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps),
+                     "separate_per_array_launches": {
+                         "imaging": per_step(tim_k, lib.TIMER_IMAGE, args.steps),
+                         "calibration_solve": per_step(tim_k, lib.TIMER_SOLVE, args.steps),
+                         "image_reduce": per_step(tim_k, lib.TIMER_REDUCE, args.steps)}} if fused else
+                    {"imaging": per_step(tim, lib.TIMER_IMAGE, args.steps),
+                     "calibration_solve": per_step(tim, lib.TIMER_SOLVE, args.steps),
+                     "image_reduce": per_step(tim, lib.TIMER_REDUCE, args.steps)}),
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "forms": forms,

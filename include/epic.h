@@ -254,12 +254,28 @@ int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
  *   EPIC_OPT_GRAPH       1 = epic_run captures its batched launches in a hipGraph
  *                        on a plan-owned stream (ordered after and before the
  *                        caller's stream by events) and replays it while the
- *                        buffers and n_samples stay the same. */
+ *                        buffers and n_samples stay the same.
+ *   EPIC_OPT_OVERLAP     1 (default) = where every array of the plan allows it
+ *                        (one tapped pixel, no band, more than 64 antennas or
+ *                        intervals longer than 8 samples, an imaging engine of
+ *                        the persistent kernel, the FFT transform) and the
+ *                        plan's channels number fewer than the GPU's CUs (the
+ *                        solve, one workgroup per channel, leaves CUs idle),
+ *                        epic_run makes one launch for the calibration solve
+ *                        and the imaging: the solve of each channel publishes
+ *                        each interval's calibration as soon as it is known and
+ *                        the imaging of a time split starts once its intervals
+ *                        are published, so that the imaging runs on the CUs the
+ *                        solve leaves free; results equal the separate launches'
+ *                        (gains bit for bit, images within rounding).  Timing
+ *                        then counts the one launch as imaging.  0 = separate
+ *                        launches.  epic_run_noalloc never fuses. */
 #define EPIC_OPT_SPLITS 1
 #define EPIC_OPT_TRANSFORM 2
 #define EPIC_OPT_TIMING 3
 #define EPIC_OPT_BATCH 4
 #define EPIC_OPT_GRAPH 5
+#define EPIC_OPT_OVERLAP 6
 int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 
 /* Kernel timing, when EPIC_OPT_TIMING is on.  Events are recorded on the

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libepic.so")
 
-SOURCES = ["epic_api.hip", "k_image.hip", "k_adjoint.hip", "k_solve.hip", "k_dft.hip", "k_batch.hip"]
+SOURCES = ["epic_api.hip", "k_image.hip", "k_adjoint.hip", "k_solve.hip", "k_dft.hip", "k_batch.hip", "k_fused.hip"]
 ARCH = "gfx950"
 
 

@@ -38,7 +38,17 @@ __device__ __forceinline__ T gload(const T* p) {
 }
 template <typename T>
 __device__ __forceinline__ void gstore(T* p, T v) {
-  *(__attribute__((address_space(1))) T*)p = v;
+  if constexpr (sizeof(T) == 8 && alignof(T) >= 8) {
+    gvec2 w;
+    __builtin_memcpy(&w, &v, 8);
+    *(__attribute__((address_space(1))) gvec2*)p = w;
+  } else if constexpr (sizeof(T) == 16 && alignof(T) >= 16) {
+    gvec4 w;
+    __builtin_memcpy(&w, &v, 16);
+    *(__attribute__((address_space(1))) gvec4*)p = w;
+  } else {
+    *(__attribute__((address_space(1))) T*)p = v;
+  }
 }
 
 // A raw packed sample held in registers until it is used (so that a prefetch

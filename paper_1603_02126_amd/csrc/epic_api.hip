@@ -512,6 +512,7 @@ struct epic_plan_s {
   int transform = 0;
   int batch = 0;             // 0 auto (batched when >1 array), 1 on, 2 off
   bool graph = false;
+  bool overlap = true;       // the fused solve + imaging launch where every array allows it
   bool timing = false;
   std::vector<TimerRec> timers;
   std::vector<hipEvent_t> event_pool;
@@ -522,6 +523,8 @@ struct epic_plan_s {
   std::vector<int> items_key;
   bool items_built = false;
   int* d_counter = nullptr;
+  int* d_fused = nullptr;    // fused run: role ticket, error word, per-channel progress
+  int fused_cap = 0;
   // captured graph and the private stream it runs on
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -668,10 +671,18 @@ int units_for(const ArrayPlan& ap) { return epic::cls_groups(engine_probe(ap), a
 // Frames a workgroup images at once.
 int slots_for(int N) { return N >= 128 ? 1 : 4 * (64 / N); }
 
-int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0) {
+int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0, bool fused = false) {
   const int F = ap.h.F, N = ap.h.nx;
   if (tuned > 0) return int(std::max<int64_t>(1, std::min<int64_t>(tuned, std::max<int64_t>(1, T))));
   if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
+  if (fused) {
+    // the fused run pulls items dynamically, solve workgroups joining late:
+    // twice the items of the separate launch keep the last ones short
+    // (LWA shape: 16 splits 6.20 ms, 32 splits 6.07 ms per fused launch)
+    const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
+    const int64_t s2 = 2 * int64_t(pick_splits(p, ap, T, 0, false));
+    return int(std::max<int64_t>(1, std::min<int64_t>(s2, std::max<int64_t>(1, T / per_split))));
+  }
   // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames
   // per slot; at 64 x 64 (the two-waves-per-SIMD engines: eight waves) >= 16
   // frames per wave, which repays a workgroup's set-up and reduction (the
@@ -888,6 +899,7 @@ int epic_plan_destroy(epic_plan_t plan) {
   if (plan->gstream) hipStreamDestroy(plan->gstream);
   hipFree(plan->d_items);
   hipFree(plan->d_counter);
+  hipFree(plan->d_fused);
   delete plan;
   return EPIC_OK;
 }
@@ -1065,6 +1077,11 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
     case EPIC_OPT_GRAPH:
       plan->graph = value != 0;
       return EPIC_OK;
+    case EPIC_OPT_OVERLAP:
+      if (value != 0 && value != 1) return fail(EPIC_ERR_ARG, "EPIC_OPT_OVERLAP is 0 or 1");
+      if (plan->overlap != (value != 0)) plan->generation++;
+      plan->overlap = value != 0;
+      return EPIC_OK;
     default:
       return fail(EPIC_ERR_ARG, "unknown option key %d", key);
   }
@@ -1227,6 +1244,30 @@ static int body_of(epic_plan_t plan, const ArrayPlan& ap) {
 
 static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) { return body_of(plan, ap) == 0; }
 
+// The fused run (one launch for the solve and the imaging) applies when every
+// array takes the single-pixel solve of kSolveMainThreads threads (no band,
+// one tapped pixel, not the one-wave solve of tiny arrays) and is imaged by a
+// body of the persistent kernel, and pays when the separate solve launch
+// would leave CUs idle: fewer solve tasks (channels of all arrays) than CUs.
+// With more, the solve fills the chip by itself and the fused run only adds
+// the cost of finer imaging items (HERA shape, 512 channels: 23.0 against
+// 22.8 ms; eight uneven arrays of 256 channels: 61.3 against 61.1 ms).
+static bool fused_eligible(epic_plan_t plan) {
+  if (!plan->overlap || plan->arrays.size() > size_t(epic::kMaxBatch)) return false;
+  int n_chan = 0;
+  for (const ArrayPlan& ap : plan->arrays) n_chan += ap.h.F;
+  if (n_chan >= plan->n_cu) return false;
+  for (const ArrayPlan& ap : plan->arrays) {
+    if (ap.band_mode != EPIC_BAND_NONE || ap.n_pix != 1 || own_launch(plan, ap)) return false;
+    epic::SolveArgs probe{};
+    probe.Na = ap.h.na;
+    probe.n_pix = 1;
+    probe.t_cal = ap.t_cal;
+    if (epic::solve_by_wave(probe)) return false;
+  }
+  return true;
+}
+
 // Work items {array, channel, class group, split}, most expensive first;
 // none for the arrays with their own launch.
 static int build_items(epic_plan_t plan, const std::vector<RunLayout>& lay, int64_t n_samples) {
@@ -1336,10 +1377,69 @@ static int layout_array(const ArrayPlan& ap, int64_t n_samples, int splits, size
   return EPIC_OK;
 }
 
-// Enqueue the whole run on `s`; batched selects the one-launch-per-stage form.
+// The reduction of every array's partial images (batched and fused runs).
+static int enqueue_reduce_batch(epic_plan_t plan, const std::vector<RunLayout>& lay, char* scr, int64_t n_samples,
+                                float* const* image, hipStream_t s, bool timed, const int* error) {
+  const int na_arr = int(plan->arrays.size());
+  epic::BatchReduceArgs b{};
+  b.n_arrays = na_arr;
+  b.off[0] = 0;
+  for (int i = 0; i < na_arr; ++i) {
+    const HostArray& h = plan->arrays[i].h;
+    b.partial[i] = reinterpret_cast<const float*>(scr + lay[i].p_off);
+    b.image[i] = image[i];
+    b.splits[i] = lay[i].splits;
+    b.per_split[i] = int64_t(h.F) * h.nx * h.ny;
+    b.scale[i] = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
+    b.off[i + 1] = b.off[i] + b.per_split[i];
+  }
+  b.error = error;
+  Timed tm(plan, EPIC_TIMER_REDUCE, s, timed);
+  hipError_t e = epic::launch_reduce_batch(b, s);
+  return e == hipSuccess ? EPIC_OK : hip_fail(e, "batched reduction launch");
+}
+
+// The fused run: one launch for the calibration solve and the imaging of
+// every array (the solve publishes u interval by interval, the imaging items
+// wait for the intervals they need), then the reduction.  Timed as imaging.
+static int enqueue_fused(epic_plan_t plan, const std::vector<RunLayout>& lay, char* scr,
+                         const std::vector<epic::SolveArgs>& sa, const void* const* efield, int64_t n_samples,
+                         float* const* image, hipStream_t s, bool timed) {
+  const int na_arr = int(plan->arrays.size());
+  epic::BatchImageArgs b{};
+  epic::FusedArgs fa{};
+  b.n_arrays = na_arr;
+  fa.chan_off[0] = 0;
+  for (int i = 0; i < na_arr; ++i) {
+    ArrayPlan& ap = plan->arrays[i];
+    b.arr[i] = image_args(plan, ap, efield[i], n_samples, reinterpret_cast<const float2*>(scr + lay[i].u_off),
+                          ap.t_cal, reinterpret_cast<float*>(scr + lay[i].p_off), lay[i].splits);
+    b.code[i] = body_of(plan, ap);
+    const epic::SolveArgs& a = sa[i];
+    fa.sx[i] = epic::FusedSolveExtra{a.A, a.D, a.hold, a.gains, a.g_hist, a.status, a.na_eff, a.gamma, a.n_int,
+                                     100 * epic::solve_main_j(ap.h.na) + solve_ps(ap.h)};
+    fa.chan_off[i + 1] = fa.chan_off[i] + ap.h.F;
+  }
+  fa.n_solve = fa.chan_off[na_arr];
+  fa.ticket = plan->d_fused;
+  fa.error = plan->d_fused + 1;
+  fa.progress = plan->d_fused + 64;
+  b.items = plan->d_items;
+  b.n_items = plan->n_items;
+  b.counter = plan->d_counter;
+  {
+    Timed tm(plan, EPIC_TIMER_IMAGE, s, timed);
+    hipError_t e = epic::launch_run_fused(b, fa, plan->n_cu, s);
+    if (e != hipSuccess) return hip_fail(e, "fused solve and imaging launch");
+  }
+  return enqueue_reduce_batch(plan, lay, scr, n_samples, image, s, timed, fa.error);
+}
+
+// Enqueue the whole run on `s`; batched selects the one-launch-per-stage form,
+// fused the one launch for the solve and the imaging.
 static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char* scr, const void* const* efield,
                        int64_t n_samples, double* const* gains, float* const* image, double* const* gain_hist,
-                       uint32_t* const* ant_status, hipStream_t s, bool batched, bool timed) {
+                       uint32_t* const* ant_status, hipStream_t s, bool batched, bool timed, bool fused = false) {
   const int na_arr = int(plan->arrays.size());
   std::vector<epic::SolveArgs> sa(na_arr);
   for (int i = 0; i < na_arr; ++i)
@@ -1350,6 +1450,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
     const HostArray& h = plan->arrays[i].h;
     return epic::launch_hist_to_u(sa[i].g_hist, plan->arrays[i].d_hold, lay[i].n_int, h.F, h.na, sa[i].u_hist, s);
   };
+  if (fused) return enqueue_fused(plan, lay, scr, sa, efield, n_samples, image, s, timed);
   if (!batched) {
     for (int i = 0; i < na_arr; ++i) {
       ArrayPlan& ap = plan->arrays[i];
@@ -1369,10 +1470,10 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
   {
     Timed tm(plan, EPIC_TIMER_SOLVE, s, timed);
     bool same = true;
-    const int j0 = plan->arrays[0].h.na > 1024 ? 2 : 1, ps0 = solve_ps(plan->arrays[0].h);
+    const int j0 = epic::solve_main_j(plan->arrays[0].h.na), ps0 = solve_ps(plan->arrays[0].h);
     for (int i = 1; i < na_arr; ++i)
-      same = same && (plan->arrays[i].h.na > 1024 ? 2 : 1) == j0 && solve_ps(plan->arrays[i].h) == ps0;
-    for (int i = 0; i < na_arr; ++i) same = same && !epic::solve_by_wave(sa[i]);
+      same = same && epic::solve_main_j(plan->arrays[i].h.na) == j0 && solve_ps(plan->arrays[i].h) == ps0;
+    for (int i = 0; i < na_arr; ++i) same = same && !epic::solve_by_wave(sa[i]) && sa[i].n_pix == 1;
     if (same) {
       epic::BatchSolveArgs b{};
       b.n_arrays = na_arr;
@@ -1424,24 +1525,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
     hipError_t e = epic::launch_image_batch(b, plan->n_cu, s);
     if (e != hipSuccess) return hip_fail(e, "batched imaging launch");
   }
-  {
-    epic::BatchReduceArgs b{};
-    b.n_arrays = na_arr;
-    b.off[0] = 0;
-    for (int i = 0; i < na_arr; ++i) {
-      const HostArray& h = plan->arrays[i].h;
-      b.partial[i] = reinterpret_cast<const float*>(scr + lay[i].p_off);
-      b.image[i] = image[i];
-      b.splits[i] = lay[i].splits;
-      b.per_split[i] = int64_t(h.F) * h.nx * h.ny;
-      b.scale[i] = 1.0 / (double(n_samples) * double(h.na_eff) * double(h.na_eff));
-      b.off[i + 1] = b.off[i] + b.per_split[i];
-    }
-    Timed tm(plan, EPIC_TIMER_REDUCE, s, timed);
-    hipError_t e = epic::launch_reduce_batch(b, s);
-    if (e != hipSuccess) return hip_fail(e, "batched reduction launch");
-  }
-  return EPIC_OK;
+  return enqueue_reduce_batch(plan, lay, scr, n_samples, image, s, timed, nullptr);
 }
 
 // Argument checks of a run over every array of the plan and its scratch
@@ -1449,7 +1533,7 @@ static int enqueue_run(epic_plan_t plan, const std::vector<RunLayout>& lay, char
 static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, double* const* gains,
                        float* const* image, double* const* gain_hist, uint32_t* const* ant_status,
                        std::vector<RunLayout>& lay, size_t& need, bool& all_batchable, bool& any_band,
-                       const std::vector<int>* splits = nullptr) {
+                       const std::vector<int>* splits = nullptr, bool fused = false) {
   if (!plan) return fail(EPIC_ERR_ARG, "plan is NULL");
   if (!efield || !gains || !image) return fail(EPIC_ERR_ARG, "efield, gains and image arrays must not be NULL");
   if (n_samples < 1) return fail(EPIC_ERR_ARG, "n_samples must be >= 1");
@@ -1472,7 +1556,7 @@ static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_sa
                              {ant_status ? ant_status[i] : nullptr, "ant_status"}})))
       return rc;
     const int sp = splits && (*splits)[i] > 0 ? (*splits)[i]
-                                                : pick_splits(plan, ap, n_samples, ap.tune_splits);
+                                                : pick_splits(plan, ap, n_samples, ap.tune_splits, fused);
     rc = layout_array(ap, n_samples, sp, size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
   }
@@ -1484,29 +1568,48 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
   std::vector<RunLayout> lay;
   size_t need = 0;
   bool all_batchable = false, any_band = false;
+  const bool fused_plan = plan && plan->arrays.size() <= size_t(epic::kMaxBatch) && fused_eligible(plan);
   int rc = prepare_run(plan, efield, n_samples, gains, image, gain_hist, ant_status, lay, need, all_batchable,
-                       any_band);
+                       any_band, nullptr, fused_plan);
   if (rc) return rc;
   const int na_arr = int(plan->arrays.size());
   if (any_band && plan->batch == 1)
     return fail(EPIC_ERR_UNSUPPORTED, "gains shared over a band run in the per-array form (EPIC_OPT_BATCH 0 or 2)");
+  const bool fused = !any_band && all_batchable && fused_eligible(plan);
   const bool batched = !any_band && all_batchable && (plan->batch == 1 || (plan->batch == 0 && na_arr > 1));
-  if (plan->graph && !batched)
+  if (plan->graph && !batched && !fused)
     return fail(EPIC_ERR_UNSUPPORTED, "graph replay needs the batched form (EPIC_OPT_BATCH and supported engines)");
   void* scr = nullptr;
   rc = plan_scratch(plan, need, &scr);
   if (rc) return rc;
-  if (batched) {
+  if (batched || fused) {
     if (!plan->d_counter) {
       if (hipMalloc(&plan->d_counter, 256) != hipSuccess) return fail(EPIC_ERR_ALLOC, "counter allocation failed");
       plan->generation++;
     }
     if ((rc = build_items(plan, lay, n_samples))) return rc;
   }
+  if (fused) {
+    int n_chan = 0;
+    for (const ArrayPlan& ap : plan->arrays) n_chan += ap.h.F;
+    if (64 + n_chan > plan->fused_cap) {
+      if (plan->d_fused) {
+        hipError_t e = hipDeviceSynchronize();   // a launch of an earlier call may still use the old buffer
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before the progress buffer is replaced");
+        hipFree(plan->d_fused);
+        plan->d_fused = nullptr;
+        plan->fused_cap = 0;
+      }
+      if (hipMalloc(&plan->d_fused, size_t(64 + n_chan) * sizeof(int)) != hipSuccess)
+        return fail(EPIC_ERR_ALLOC, "progress buffer allocation failed");
+      plan->fused_cap = 64 + n_chan;
+      plan->generation++;
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!plan->graph)
     return enqueue_run(plan, lay, static_cast<char*>(scr), efield, n_samples, gains, image, gain_hist, ant_status, s,
-                       batched, true);
+                       batched, true, fused);
 
   // hipGraph: capture once per (buffers, n_samples, plan memory generation), replay afterwards
   if (!plan->gstream) {
@@ -1533,7 +1636,7 @@ int epic_run(epic_plan_t plan, const void* const* efield, int64_t n_samples, dou
     hipError_t e = hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     rc = enqueue_run(plan, lay, static_cast<char*>(scr), efield, n_samples, gains, image, gain_hist, ant_status,
-                     plan->gstream, true, false);
+                     plan->gstream, true, false, fused);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(plan->gstream, &g);
     if (rc) {

@@ -173,7 +173,42 @@ struct BatchReduceArgs {
   double scale[kMaxBatch];
   int64_t off[kMaxBatch + 1];
   int n_arrays;
+  const int* error = nullptr;   // nonzero: the images are not valid (written as NaN)
 };
+
+// One launch for the calibration solve and the imaging of every array.  The
+// first workgroups to start take the solve tasks (one channel each), publish
+// each interval's FP32 u = 1/g as soon as it is known and raise the
+// channel's progress counter; every workgroup then pulls imaging items, each
+// waiting until the intervals its samples fall in are published.  A solve
+// never waits, and every solve task is taken before any workgroup images, so
+// the waits always end; each is bounded all the same and, if it runs out,
+// sets *error (the reduction then writes NaN images).
+// The solve fields that the array's ImageArgs does not already carry:
+struct FusedSolveExtra {
+  const double2* A;
+  const double2* D;
+  const uint8_t* hold;
+  double2* gains;
+  double2* g_hist;
+  uint32_t* status;
+  double na_eff, gamma;
+  int n_int;
+  int code;                 // 100 J + PS of the single-pixel solve body
+};
+
+struct FusedArgs {
+  FusedSolveExtra sx[kMaxBatch];
+  int chan_off[kMaxBatch + 1];   // prefix sums of channel counts: solve task -> (array, channel)
+  int n_solve;
+  int* ticket;              // role counter (reset by the launcher)
+  int* progress;            // [n_solve] intervals published per channel (reset by the launcher)
+  int* error;
+};
+
+hipError_t launch_run_fused(const BatchImageArgs& b, const FusedArgs& fa, int n_workgroups, hipStream_t s);
+// the spin limit of one wait (polls of about 0.2 us each)
+constexpr int kFusedWaitPolls = 1 << 23;
 
 // Body of the persistent batched imaging kernel for an array (0: none, the
 // array is imaged by its own launch in the batched sequence).
@@ -225,6 +260,7 @@ hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
                          float* image, hipStream_t s);
 bool solve_supported(int na, int fmt, int n_pix = 1);
+int solve_main_j(int na);   // antennas per thread slot of the single-pixel solve
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 // The solve of these arrays runs one wave per channel (small arrays, short
 // intervals): launch_solve picks it, so a batched solve leaves them to it.

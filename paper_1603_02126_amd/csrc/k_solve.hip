@@ -7,9 +7,15 @@
 namespace epic {
 
 template <int J, int PS>
-__global__ __launch_bounds__(kSolveThreads) void k_solve(SolveArgs a) {
+__global__ __launch_bounds__(kSolveMainThreads) void k_solve(SolveArgs a) {
   __shared__ __align__(16) uint8_t smem[SolveSmem::BYTES];
   solve_channel<J, PS>(a, blockIdx.x, smem);
+}
+
+template <int PS>
+__global__ __launch_bounds__(kSolveThreads) void k_solve_pixels(SolveArgs a) {
+  __shared__ __align__(16) uint8_t smem[SolveSmem::BYTES];
+  solve_channel_pixels<PS>(a, blockIdx.x, smem);
 }
 
 // One wave per channel: small arrays with short intervals.
@@ -65,24 +71,37 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int MAXP>
+template <int MAXP, int T>
 static int stage_cap(int RB) {
-  return RB % 16 == 0 ? Stager<16, MAXP>::CAP : RB % 4 == 0 ? Stager<4, MAXP>::CAP : Stager<1, MAXP>::CAP;
+  return RB % 16 == 0 ? Stager<16, MAXP, T>::CAP : RB % 4 == 0 ? Stager<4, MAXP, T>::CAP : Stager<1, MAXP, T>::CAP;
 }
+
+int solve_main_j(int na) { return na <= kSolveMainThreads ? 1 : na <= 2 * kSolveMainThreads ? 2 : 4; }
 
 bool solve_supported(int na, int fmt, int n_pix) {
   const int RB = na * efmt_bytes(fmt);
-  const int cap = na <= kSolveThreads ? stage_cap<8>(RB) : stage_cap<4>(RB);   // the stagers of J = 1 and 2
-  if (n_pix < 1 || n_pix > kMaxPix || (n_pix > 1 && na > kSolveThreads)) return false;
-  return na >= 1 && na <= 2 * kSolveThreads && RB <= cap;
+  if (n_pix < 1 || n_pix > kMaxPix || na < 1) return false;
+  if (n_pix > 1) return na <= kSolveThreads && RB <= stage_cap<8, kSolveThreads>(RB);
+  // the single-pixel solve's stager (MainStageMax: 8 pieces per thread at 512 threads)
+  return na <= 4 * kSolveMainThreads && RB <= stage_cap<8, kSolveMainThreads>(RB);
 }
 
 template <int J>
 static hipError_t launch_solve_j(const SolveArgs& a, hipStream_t s) {
   const int RB = a.Na * efmt_bytes(a.fmt);
-  if (RB % 16 == 0) hipLaunchKernelGGL((k_solve<J, 16>), dim3(a.F), dim3(kSolveThreads), 0, s, a);
-  else if (RB % 4 == 0) hipLaunchKernelGGL((k_solve<J, 4>), dim3(a.F), dim3(kSolveThreads), 0, s, a);
-  else hipLaunchKernelGGL((k_solve<J, 1>), dim3(a.F), dim3(kSolveThreads), 0, s, a);
+  const dim3 blk(kSolveMainThreads);
+  if (RB % 16 == 0) hipLaunchKernelGGL((k_solve<J, 16>), dim3(a.F), blk, 0, s, a);
+  else if (RB % 4 == 0) hipLaunchKernelGGL((k_solve<J, 4>), dim3(a.F), blk, 0, s, a);
+  else hipLaunchKernelGGL((k_solve<J, 1>), dim3(a.F), blk, 0, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_solve_pixels(const SolveArgs& a, hipStream_t s) {
+  const int RB = a.Na * efmt_bytes(a.fmt);
+  const dim3 blk(kSolveThreads);
+  if (RB % 16 == 0) hipLaunchKernelGGL((k_solve_pixels<16>), dim3(a.F), blk, 0, s, a);
+  else if (RB % 4 == 0) hipLaunchKernelGGL((k_solve_pixels<4>), dim3(a.F), blk, 0, s, a);
+  else hipLaunchKernelGGL((k_solve_pixels<1>), dim3(a.F), blk, 0, s, a);
   return hipGetLastError();
 }
 
@@ -96,8 +115,9 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_solve_wave, dim3(a.F), dim3(64), 0, s, a);
     return hipGetLastError();
   }
-  if (a.Na <= kSolveThreads) return launch_solve_j<1>(a, s);
-  return launch_solve_j<2>(a, s);
+  if (a.n_pix > 1) return launch_solve_pixels(a, s);
+  const int j = solve_main_j(a.Na);
+  return j == 1 ? launch_solve_j<1>(a, s) : j == 2 ? launch_solve_j<2>(a, s) : launch_solve_j<4>(a, s);
 }
 __global__ __launch_bounds__(256) void k_hist_to_u(const double2* g_hist, const uint8_t* hold, int64_t n_elem,
                                                    int64_t per_int, float2* u_hist) {

@@ -24,17 +24,18 @@ namespace epic {
 // up to 1e4, so FP32 rounding there would move the converged gains by 1e-3.
 // The E-fields are integers (or FP32) and enter exactly.
 // ---------------------------------------------------------------------------
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 1024;       // multi-pixel and band solves
+constexpr int kSolveMainThreads = 512;    // the single-pixel solve (all its kernels and bodies)
 constexpr int kSolveChunkBytes = 32768;   // a whole interval of most arrays: one load latency per interval
 constexpr int kSolveMaxRows = 1024;
 
 // One thread's share of a chunk copy, PS bytes per piece, at most MAXP
-// pieces (registers) per thread.
-template <int PS, int MAXP>
+// pieces (registers) per thread, T threads.
+template <int PS, int MAXP, int T = kSolveThreads>
 struct Stager {
-  static constexpr int PPT0 = kSolveChunkBytes / (kSolveThreads * PS);
+  static constexpr int PPT0 = kSolveChunkBytes / (T * PS);
   static constexpr int PPT = PPT0 < MAXP ? PPT0 : MAXP;               // pieces per thread
-  static constexpr int CAP = kSolveThreads * PS * PPT;                 // bytes per chunk
+  static constexpr int CAP = T * PS * PPT;                             // bytes per chunk
   static constexpr int WPP = PS >= 4 ? PS / 4 : 1;                     // 32-bit words per piece
   uint32_t v[PPT * WPP];
   __device__ __forceinline__ void load(const uint8_t* ebase, int64_t rowstride, int64_t t_first, int nrows,
@@ -46,17 +47,17 @@ struct Stager {
     // stay in flight while the current chunk is processed
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      const int p0 = tid + k * kSolveThreads;
+      const int p0 = tid + k * T;
       const int p = p0 < total ? p0 : 0;
       const int r = p / per_row, c = p - r * per_row;
       const uint8_t* src = ebase + (t_first + r) * rowstride + c * PS;
       if constexpr (PS == 16) {
-        const uint4 w = *reinterpret_cast<const uint4*>(src);
+        const uint4 w = gload(reinterpret_cast<const uint4*>(src));
         v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
       } else if constexpr (PS == 4) {
-        v[k] = *reinterpret_cast<const uint32_t*>(src);
+        v[k] = gload(reinterpret_cast<const uint32_t*>(src));
       } else {
-        v[k] = *src;
+        v[k] = gload(src);
       }
     }
   }
@@ -65,7 +66,7 @@ struct Stager {
     const int total = nrows * per_row;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      const int p = tid + k * kSolveThreads;
+      const int p = tid + k * T;
       if (p < total) {
         const int r = p / per_row, c = p - r * per_row;
         uint8_t* d = dst + r * RB + c * PS;
@@ -132,7 +133,9 @@ __device__ __forceinline__ double2 epical_step_r(double2 Kbar, double Qbar, doub
   return gn;
 }
 
-// J = antennas per thread slot (Na <= 1024 * J), PS = chunk piece size.
+// J = antennas per thread slot (Na <= T * J), PS = chunk piece size, T =
+// threads of the workgroup (kSolveMainThreads for every single-pixel solve,
+// so that all of them sum in the same order and give identical gains).
 // LDS of one solve workgroup: two chunk buffers, the taps of a chunk and the
 // coefficients c_a (up to 2 * kSolveThreads antennas), both FP64.
 // With several tapped pixels the same areas hold the taps [kMaxPix][256]
@@ -145,8 +148,20 @@ struct SolveSmem {
   static_assert(2 * kSolveThreads <= kMaxPix * kSolveThreads, "coefficients of 2048 antennas fit");
 };
 
-template <int J, int PS, int FMT>
-__device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uint8_t* smem) {
+// Pieces per thread of the single-pixel solve's stager: registers are
+// plentiful at 512 threads (two waves per SIMD), scarcer at 1024.
+template <int J, int T>
+struct MainStageMax {
+  static constexpr int value = (J == 1 || T <= 512) ? 8 : 4;
+};
+
+// PUBLISH (the fused run): at the start of each interval the FP32 u = 1/g of
+// every antenna (zero when flagged) is written to a.u_hist, the values that
+// launch_hist_to_u would derive from the gain history, with coherent (sc1)
+// stores; once every wave's stores have completed, progress[f] = intervals
+// published, an agent-scope store the imaging workgroups poll.
+template <int J, int PS, int FMT, int T = kSolveMainThreads, bool PUBLISH = false>
+__device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uint8_t* smem, int* progress = nullptr) {
   uint8_t (*chunk)[kSolveChunkBytes] = reinterpret_cast<uint8_t (*)[kSolveChunkBytes]>(smem);
   double2* P_l = reinterpret_cast<double2*>(smem + SolveSmem::P_OFF);
   double2* c_l = reinterpret_cast<double2*>(smem + SolveSmem::C_OFF);
@@ -155,14 +170,14 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
   const int RB = a.Na * bpe;
   const int64_t rowstride = int64_t(a.F) * RB;
   const uint8_t* ebase = a.efield + int64_t(f) * RB;
-  using Stage = Stager<PS, J == 1 ? 8 : 4>;
+  using Stage = Stager<PS, MainStageMax<J, T>::value, T>;
   int rpc = Stage::CAP / RB;
   rpc = rpc < kSolveMaxRows ? rpc : kSolveMaxRows;
 
   // thread -> (antenna slot, row group); row groups of one antenna are adjacent lanes
   int NaP = 16;
-  while (NaP < a.Na && NaP < kSolveThreads) NaP <<= 1;
-  const int RG = kSolveThreads / NaP;  // <= 64
+  while (NaP < a.Na && NaP < T) NaP <<= 1;
+  const int RG = T / NaP;  // <= 64
   const int rg = tid % RG;
   const int a0 = tid / RG;
 
@@ -179,13 +194,13 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
     st[j] = 0u;
     if (an < a.Na) {
       const int64_t ia = int64_t(f) * a.Na + an;
-      g[j] = a.gains[ia];
-      A[j] = a.A[ia];
-      const double2 D = a.D[ia];
+      g[j] = gload(a.gains + ia);
+      A[j] = gload(a.A + ia);
+      const double2 D = gload(a.D + ia);
       const double d2 = D.x * D.x + D.y * D.y;
       invD[j] = make_double2(a.na_eff * D.x / d2, -a.na_eff * D.y / d2);
-      hold[j] = a.hold[ia];
-      if (rg == 0) a.g_hist[ia] = g[j];
+      hold[j] = gload(a.hold + ia);
+      if (rg == 0) gstore(a.g_hist + ia, g[j]);
     }
   }
 
@@ -218,13 +233,26 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
           double2 c = zmul(A[j], make_double2(g[j].x * rr[j], -g[j].y * rr[j]));
           if (hold[j] & kHoldFlagged) c = make_double2(0.0, 0.0);
           c_l[an] = c;
+          if constexpr (PUBLISH) {
+            double2 u = zrecip(g[j]);
+            if (hold[j] & kHoldFlagged) u = make_double2(0.0, 0.0);
+            const float2 uf = make_float2(float(u.x), float(u.y));
+            __hip_atomic_store((__attribute__((address_space(1))) uint64_t*)(a.u_hist + (int64_t(n) * a.F + f) * a.Na + an),
+                               __builtin_bit_cast(uint64_t, uf), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
       }
     }
+    if constexpr (PUBLISH) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's u stores are done
     double Kx[J], Ky[J], Q[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) Kx[j] = Ky[j] = Q[j] = 0.0;
     __syncthreads();
+    if constexpr (PUBLISH) {
+      if (tid == 0)
+        __hip_atomic_store((__attribute__((address_space(1))) int*)(progress + f), n + 1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
     for (int r0 = 0; r0 < len; r0 += rpc) {
       const int nr = min(rpc, len - r0);
       // prefetch the following chunk (this interval or the next one)
@@ -242,7 +270,7 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
       // 64 rows per pass, sums within each 16-lane DPP row
       {
         const int q = tid & 15, rr = tid >> 4;
-        for (int rb = 0; rb < nr; rb += kSolveThreads / 16) {
+        for (int rb = 0; rb < nr; rb += T / 16) {
           const int r = rb + rr;
           double px = 0.0, py = 0.0;
           if (r < nr) {
@@ -329,7 +357,7 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
         const double2 gn = epical_step_r(make_double2(Kx[j] * inv_n, Ky[j] * inv_n), Q[j] * inv_n, A[j],
                                          invD[j], g[j], rr[j], hold[j], a.gamma, &st[j]);
         g[j] = gn;
-        if (rg == 0) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + an] = gn;
+        if (rg == 0) gstore(a.g_hist + (int64_t(n + 1) * a.F + f) * a.Na + an, gn);
       }
     }
   }
@@ -338,8 +366,11 @@ __device__ __forceinline__ void solve_channel_fmt(const SolveArgs& a, int f, uin
     for (int j = 0; j < J; ++j) {
       const int an = a0 + NaP * j;
       if (an < a.Na) {
-        a.gains[int64_t(f) * a.Na + an] = g[j];
-        if (a.status) a.status[int64_t(f) * a.Na + an] |= st[j];
+        gstore(a.gains + int64_t(f) * a.Na + an, g[j]);
+        if (a.status) {
+          uint32_t* sp = a.status + int64_t(f) * a.Na + an;
+          gstore(sp, gload(sp) | st[j]);
+        }
       }
     }
   }
@@ -600,21 +631,21 @@ __device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, u
   __syncthreads();
 }
 
-// Format dispatch: the E-field format is a compile-time constant of the
-// inner loops; several tapped pixels take the multi-pixel solve (J = 1).
+// Format dispatch of the single-pixel solve (kSolveMainThreads threads): the
+// E-field format is a compile-time constant of the inner loops.
 template <int J, int PS>
 __device__ __forceinline__ void solve_channel(const SolveArgs& a, int f, uint8_t* smem) {
-  if constexpr (J == 1) {
-    if (a.n_pix > 1) {
-      if (a.fmt == kCI4) solve_channel_multi<PS, kCI4>(a, f, smem);
-      else if (a.fmt == kCI8) solve_channel_multi<PS, kCI8>(a, f, smem);
-      else solve_channel_multi<PS, kCF32>(a, f, smem);
-      return;
-    }
-  }
   if (a.fmt == kCI4) solve_channel_fmt<J, PS, kCI4>(a, f, smem);
   else if (a.fmt == kCI8) solve_channel_fmt<J, PS, kCI8>(a, f, smem);
   else solve_channel_fmt<J, PS, kCF32>(a, f, smem);
+}
+
+// Several tapped pixels (kSolveThreads threads).
+template <int PS>
+__device__ __forceinline__ void solve_channel_pixels(const SolveArgs& a, int f, uint8_t* smem) {
+  if (a.fmt == kCI4) solve_channel_multi<PS, kCI4>(a, f, smem);
+  else if (a.fmt == kCI8) solve_channel_multi<PS, kCI8>(a, f, smem);
+  else solve_channel_multi<PS, kCF32>(a, f, smem);
 }
 
 }  // namespace epic

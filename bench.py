@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "09a112be0d8c5e9e7a88443c27a79c25dfdb65bb5c48108b82154bd4ba7d4ed5",
+    "lwa": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec",
             "fetch_kib": 175059.0, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "ff4512de27187ac0625eda944ca909dba1c72e2ac59ddb3677c28b22fd33d35b",
-                      "fetch_kib": 174337.4, "fetch_scale": 2.000, "write_kib": 20488238.8, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec",
+                      "fetch_kib": 174328.0, "fetch_scale": 2.000, "write_kib": 20488233.0, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "09a112be0d8c5e9e7a88443c27a79c25dfdb65bb5c48108b82154bd4ba7d4ed5", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
 }
 
 
@@ -696,7 +696,7 @@ def bench_uneven(args, dev):
             pl.run(es, T, gs, imgs)
         return step
 
-    plan = new_plan(wls)
+    plan = new_plan(wls, {lib.OPT_BATCH: 2, lib.OPT_OVERLAP: 0} if args.per_array else None)
     imgs = images()
     dt, tim = Timer([plan])(stepper(plan, imgs), args.steps, args.warmup)
     gains_plain = [g.cpu().numpy() for g in gs]
@@ -778,14 +778,15 @@ def bench_uneven(args, dev):
                     f"{T} samples, gains every {wls[0].t_cal}",
         "frames_per_step": frames,
         "path": ("FP32 FFT, one fused solve + imaging launch for all arrays (k_run_fused)" if fused
-                 else "FP32 FFT, one launch per array per stage"),
+                 else "FP32 FFT, one launch per array per stage" if tim[lib.TIMER_IMAGE][1] >= len(wls) * args.steps
+                 else "FP32 FFT, batched: one persistent imaging launch for all arrays (k_image_batch)"),
         "parallelism": "1 GPU"})
     out.update({
         "msamples_per_s": sum(w.array.n_ant * w.array.n_chan for w in wls) * T / (dt / args.steps) / 1e6,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel": "imaging kernels of all arrays (FFT, residue-class engines), timed as "
-                               "separate per-array launches",
+                     "kernel": "imaging kernels of all arrays (FFT, residue-class engines)" +
+                               (", timed as separate per-array launches" if fused else ""),
                      "imaging_ms_per_step": img_ms,
                      "algorithmic_bytes_per_step": bytes_step,
                      "hbm_frac": bytes_step / (img_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
@@ -888,6 +889,8 @@ def main():
                     help="tapped pixels of EPICal (lwa/hera/tiny; > 1: calibrator plus brightest sources)")
     ap.add_argument("--snapshot", type=int, default=0,
                     help="t_acc > 0: time epic_run_snapshots (one image per t_acc samples) on lwa/tiny")
+    ap.add_argument("--per-array", action="store_true",
+                    help="uneven: time one launch per array and stage (no batching, no fused run)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -276,6 +276,14 @@ int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
 #define EPIC_OPT_BATCH 4
 #define EPIC_OPT_GRAPH 5
 #define EPIC_OPT_OVERLAP 6
+/* EPIC_OPT_WAIT_POLLS  the bound of one wait of the fused run's imaging for
+ *                      the calibration it needs, in polls of about 0.2 us
+ *                      (0 = the default, 2^23, about 2 s; the waits always end
+ *                      well before it).  A wait that reaches the bound gives
+ *                      up, and the run writes NaN images (the gains are not
+ *                      affected); a small bound makes that path testable.
+ *                      Values above the default give EPIC_ERR_ARG. */
+#define EPIC_OPT_WAIT_POLLS 7
 int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value);
 
 /* Kernel timing, when EPIC_OPT_TIMING is on.  Events are recorded on the

@@ -513,6 +513,7 @@ struct epic_plan_s {
   int batch = 0;             // 0 auto (batched when >1 array), 1 on, 2 off
   bool graph = false;
   bool overlap = true;       // the fused solve + imaging launch where every array allows it
+  int fused_polls = epic::kFusedWaitPolls;   // bound of one wait of the fused run
   bool timing = false;
   std::vector<TimerRec> timers;
   std::vector<hipEvent_t> event_pool;
@@ -1082,6 +1083,13 @@ int epic_plan_set_option(epic_plan_t plan, int32_t key, int64_t value) {
       if (plan->overlap != (value != 0)) plan->generation++;
       plan->overlap = value != 0;
       return EPIC_OK;
+    case EPIC_OPT_WAIT_POLLS:
+      if (value < 0 || value > epic::kFusedWaitPolls)
+        return fail(EPIC_ERR_ARG, "EPIC_OPT_WAIT_POLLS must be in [0, %d]", epic::kFusedWaitPolls);
+      if (value == 0) value = epic::kFusedWaitPolls;
+      if (plan->fused_polls != int(value)) plan->generation++;
+      plan->fused_polls = int(value);
+      return EPIC_OK;
     default:
       return fail(EPIC_ERR_ARG, "unknown option key %d", key);
   }
@@ -1424,6 +1432,7 @@ static int enqueue_fused(epic_plan_t plan, const std::vector<RunLayout>& lay, ch
   fa.ticket = plan->d_fused;
   fa.error = plan->d_fused + 1;
   fa.progress = plan->d_fused + 64;
+  fa.max_polls = plan->fused_polls;
   b.items = plan->d_items;
   b.n_items = plan->n_items;
   b.counter = plan->d_counter;

@@ -204,6 +204,7 @@ struct FusedArgs {
   int* ticket;              // role counter (reset by the launcher)
   int* progress;            // [n_solve] intervals published per channel (reset by the launcher)
   int* error;
+  int max_polls;            // bound of one wait (kFusedWaitPolls unless set for a test)
 };
 
 hipError_t launch_run_fused(const BatchImageArgs& b, const FusedArgs& fa, int n_workgroups, hipStream_t s);

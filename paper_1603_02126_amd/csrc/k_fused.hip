@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_run_fused(BatchImageArgs b, F
       const int* p = fa.progress + fa.chan_off[w.x] + w.y;
       int polls = 0;
       while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-        if (++polls > kFusedWaitPolls) {
+        if (++polls > fa.max_polls) {
           __hip_atomic_store(fa.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }

@@ -23,7 +23,7 @@ EPIC_OK, EPIC_ERR_ARG, EPIC_ERR_ALLOC, EPIC_ERR_HIP, EPIC_ERR_UNSUPPORTED, EPIC_
 _NAMES = {EPIC_ERR_ARG: "EPIC_ERR_ARG", EPIC_ERR_ALLOC: "EPIC_ERR_ALLOC", EPIC_ERR_HIP: "EPIC_ERR_HIP",
           EPIC_ERR_UNSUPPORTED: "EPIC_ERR_UNSUPPORTED", EPIC_ERR_STATE: "EPIC_ERR_STATE"}
 CF32, CI8, CI4 = 0, 1, 2
-OPT_SPLITS, OPT_TRANSFORM, OPT_TIMING, OPT_BATCH, OPT_GRAPH, OPT_OVERLAP = 1, 2, 3, 4, 5, 6
+OPT_SPLITS, OPT_TRANSFORM, OPT_TIMING, OPT_BATCH, OPT_GRAPH, OPT_OVERLAP, OPT_WAIT_POLLS = 1, 2, 3, 4, 5, 6, 7
 TIMER_SOLVE, TIMER_IMAGE, TIMER_REDUCE, TIMER_ADJOINT, TIMER_GRAPH, TIMER_COUNT = 0, 1, 2, 3, 4, 5
 ANT_FLAGGED, ANT_D_ZERO, ANT_NONFINITE, ANT_BAND_HELD, ANT_BARRIER = 1, 2, 4, 8, 16
 BAND_NONE, BAND_MEAN, BAND_POLY, BAND_MAX_DEG = 0, 1, 2, 3

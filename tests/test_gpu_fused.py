@@ -110,3 +110,28 @@ def test_ineligible_plan_runs_separately(cuda):
         gpu_run(wl, packed, cuda, plan=plan)
         tim = plan.timing()
         assert tim[lib.TIMER_SOLVE][1] == 1      # its own solve launch
+
+
+def test_fused_wait_bound_gives_nan_images_not_a_hang(cuda):
+    """The imaging's bounded wait for the calibration, forced short from the
+    host: every kernel still ends, the gains are those of the separate
+    launches bit for bit, and the images are either the right ones (every wait
+    ended in time) or NaN throughout (a wait gave up), never a silent mix."""
+    from paper_1603_02126_amd import lib
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, kernel=2, n_ant=200, n_chan=3, n_samples=301, t_cal=100)
+    packed = synth.make_efield(wl)
+    sep = _plan([wl], 0)
+    (hs,), (ims,) = _run(sep, [wl], [packed], cuda)
+    sep.close()
+    short = _plan([wl], 1, {lib.OPT_WAIT_POLLS: 1})
+    (hf,), (imf,) = _run(short, [wl], [packed], cuda)
+    np.testing.assert_array_equal(hf, hs)
+    assert np.isnan(imf).all() or image_err(imf, ims).max() <= 1e-6
+    # back to the default bound: the same plan runs clean again
+    short.set_option(lib.OPT_WAIT_POLLS, 0)
+    (hf,), (imf,) = _run(short, [wl], [packed], cuda)
+    np.testing.assert_array_equal(hf, hs)
+    assert image_err(imf, ims).max() <= 1e-6
+    with pytest.raises(lib.EpicError):
+        short.set_option(lib.OPT_WAIT_POLLS, (1 << 23) + 1)
+    short.close()

@@ -164,7 +164,7 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
 // Eight waves: two frames (samples t, t + 1) x four classes of the class
 // group.  Each wave grids its class of its frame through half a 64 x 64 frame
 // (sub-cell columns 0..31, then 32..63, two schedules built on the host), runs
-// the row FFTs, transposes in registers (xpose.h, the half frame as staging)
+// the row FFTs, transposes through the half frame (xpose.h)
 // and runs the column FFTs, as the 64 x 64 paired engine does.  The E' of the
 // two frames is staged once per frame by its four waves; two workgroup
 // barriers per pair of samples order the staging against the gridding.
@@ -315,7 +315,6 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     fft_reg<NF, +1>(v);
     __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);
     fetch_raw(t + 2);
@@ -354,7 +353,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
 // and five twiddles serve eight classes (R = 4), against one table entry, one
 // E' and one twiddle per contribution and class when each wave grids its own
 // class.  Each wave then takes its class's half rows, runs the row FFTs,
-// transposes in registers and runs the column FFTs, as the paired engines do.
+// transposes through the half frame and runs the column FFTs, as the paired engines do.
 // The E' of a frame (up to 2048 complex values) and the eight half frames
 // fill the LDS, so the schedules are read from memory (the same rows for
 // every workgroup of the array: cache resident), each batch of entries
@@ -521,7 +520,6 @@ __device__ __forceinline__ void image_cls_dense_item(const ImageArgs& a, int f, 
     take_half_row<32>(v, H, lam);
     fft_reg<64, +1>(v);
     transpose64(v, H, lam);
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     fft_reg<64, +1>(v);
     fetch_raw(t + NF);
     static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });

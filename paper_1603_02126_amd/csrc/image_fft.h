@@ -92,8 +92,8 @@ namespace epic {
 //   * gridding goes through half a frame (32 columns): the columns 0..31 are
 //     gridded, then every lane loads the half of its row y = lane and clears
 //     it; then the columns 32..63 (two schedules, built on the host);
-//   * after the row FFTs the frame is transposed in registers (xpose.h),
-//     with the same half buffer as staging for the low index bits;
+//   * after the row FFTs the frame is transposed (xpose.h) through the same
+//     half buffer, one component at a time, which leaves it zero;
 //   * column FFTs and |X|^2 accumulation as in the one-wave engine.
 // Waves never wait for each other inside the frame loop.  Integer E-field
 // formats (ci4, ci8) with 129..256 antennas (four per lane).
@@ -169,7 +169,6 @@ __device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t t
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along x: lane = row y
     transpose64(v, H, lam);       // lane = column kx (normal priority: measured faster)
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     fft_reg<N, +1>(v);            // along y
     // the next frame's samples are requested here rather than at staging:
     // their registers would otherwise stay live through both FFTs
@@ -374,7 +373,6 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);
     transpose64(v, H, lam);
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     fft_reg<N, +1>(v);
     SnapCursor nxt = cur;
     nxt.next();

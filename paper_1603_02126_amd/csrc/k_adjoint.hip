@@ -190,7 +190,6 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint_pair(AdjointArgs a) {
     fft_reg<N, +1>(v);            // along x: lane = row y
     __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);       // lane = column kx
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, +1>(v);            // along y: v[ky] = X(kx = lane, ky)
     fetch_raw(t + INFLIGHT);
@@ -212,7 +211,6 @@ __global__ __launch_bounds__(kPairThreads) void k_adjoint_pair(AdjointArgs a) {
     fft_reg<N, -1>(v);            // conjugate transform along y: v[y], kx = lane
     __builtin_amdgcn_s_setprio(1);
     transpose64(v, H, lam);       // lane = row y, v[kx]
-    static_for<0, 16>([&](auto mc) { H[lam * kXposePitch + decltype(mc)::value] = make_float2(0.f, 0.f); });
     __builtin_amdgcn_s_setprio(0);
     fft_reg<N, -1>(v);            // along x: v[x] = G'(x, y = lane)
     __builtin_amdgcn_s_setprio(1);

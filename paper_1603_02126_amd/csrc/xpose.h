@@ -6,12 +6,13 @@
 // lane stores its row of real parts (64 x 65 floats: the odd pitch puts both
 // the row stores and the column loads of a wave on 64 distinct banks), loads
 // its column, and the same for the imaginary parts.  The staging area is
-// zero again on exit (each lane clears the column it loaded).  Exchanging the
+// zero again on exit: the imaginary parts are loaded by LDS exchanges with
+// zero (lds_take).  Exchanging the
 // upper index bits with v_permlane16_swap / v_permlane32_swap instead, with
 // LDS only for the low four bits, measured 9% slower on the 64 x 64 imaging
 // kernel: a wave spent about ten SIMD cycles per swap.
 #pragma once
-#include "fft_reg.h"
+#include "engine.h"
 
 namespace epic {
 
@@ -32,9 +33,7 @@ __device__ __forceinline__ void transpose64(float2 (&v)[64], float2* T, int lane
   xpose_lds_sync();
   static_for<0, 64>([&](auto kc) { F[wbase + decltype(kc)::value] = v[decltype(kc)::value].y; });
   xpose_lds_sync();
-  static_for<0, 64>([&](auto yc) { v[decltype(yc)::value].y = F[decltype(yc)::value * kXposePitch + lane]; });
-  xpose_lds_sync();
-  static_for<0, 64>([&](auto yc) { F[decltype(yc)::value * kXposePitch + lane] = 0.f; });
+  static_for<0, 64>([&](auto yc) { v[decltype(yc)::value].y = lds_take(F + decltype(yc)::value * kXposePitch + lane); });
 }
 
 }  // namespace epic

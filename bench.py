@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec",
-            "fetch_kib": 175059.0, "fetch_scale": 2.000, "write_kib": 81920.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec",
-                      "fetch_kib": 174328.0, "fetch_scale": 2.000, "write_kib": 20488233.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0",
+            "fetch_kib": 175057.6, "fetch_scale": 2.000, "write_kib": 61440.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0",
+                      "fetch_kib": 174342.5, "fetch_scale": 2.000, "write_kib": 20480090.0, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "2b71eaab0e3c8397fe7aa9b0efef7fd06e592045760f025701370f6b0447e1ec", "valu_issue_frac": 0.52, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0", "valu_issue_frac": 0.60, "lds_busy_frac": 0.52},
 }
 
 

@@ -16,7 +16,7 @@
 namespace epic {
 
 template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
+__host__ __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (B < E) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
@@ -63,24 +63,24 @@ constexpr double sin2pi(long m, long n) {
 constexpr float kInvSqrt2 = 0.70710678118654752440f;
 
 // ---- complex helpers ------------------------------------------------------
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
 
 // multiply by S*i
 template <int S>
-__device__ __forceinline__ float2 mul_si(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_si(float2 a) {
   if constexpr (S > 0) return make_float2(-a.y, a.x);
   else return make_float2(a.y, -a.x);
 }
 
 // v * exp(S 2 pi i M / N), special-casing the multiples of 2 pi / 8
 template <int M, int N, int S>
-__device__ __forceinline__ float2 twiddle(float2 v) {
+__host__ __device__ __forceinline__ float2 twiddle(float2 v) {
   constexpr int m = ((M % N) + N) % N;
   if constexpr (m == 0) {
     return v;
@@ -107,14 +107,14 @@ __device__ __forceinline__ float2 twiddle(float2 v) {
 
 // ---- small DFTs, natural order in place -----------------------------------
 template <int S>
-__device__ __forceinline__ void dft2(float2* x) {
+__host__ __device__ __forceinline__ void dft2(float2* x) {
   const float2 a = x[0], b = x[1];
   x[0] = cadd(a, b);
   x[1] = csub(a, b);
 }
 
 template <int S>
-__device__ __forceinline__ void dft4(float2* x) {
+__host__ __device__ __forceinline__ void dft4(float2* x) {
   const float2 s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
   const float2 s13 = cadd(x[1], x[3]), d13 = mul_si<S>(csub(x[1], x[3]));
   x[0] = cadd(s02, s13);
@@ -124,7 +124,7 @@ __device__ __forceinline__ void dft4(float2* x) {
 }
 
 template <int S>
-__device__ __forceinline__ void dft8(float2* x) {
+__host__ __device__ __forceinline__ void dft8(float2* x) {
   float2 e[4] = {x[0], x[2], x[4], x[6]};
   float2 o[4] = {x[1], x[3], x[5], x[7]};
   dft4<S>(e);
@@ -138,7 +138,7 @@ __device__ __forceinline__ void dft8(float2* x) {
 }
 
 template <int R, int S>
-__device__ __forceinline__ void dft_small(float2* x) {
+__host__ __device__ __forceinline__ void dft_small(float2* x) {
   if constexpr (R == 1) {
   } else if constexpr (R == 2) {
     dft2<S>(x);
@@ -157,12 +157,117 @@ struct FftSplit {
   static constexpr int R2 = N / R1;
 };
 
+// ---- 64 points with the twiddles folded into fused multiply-adds ----------
+// The split 64 = 8 x 8 of fft_reg below, with each inter-stage twiddle
+// w = exp(i theta) written as sigma * (1 + i tau) (tau = tan theta, sigma =
+// cos theta, where |cos theta| >= |sin theta|) or sigma * (kappa + i)
+// (kappa = cot theta, sigma = sin theta, otherwise).  The first stage applies
+// only the unit-diagonal factor (two FMAs instead of a complex multiply of
+// four instructions); the scales sigma, all compile-time constants of
+// magnitude in [1/sqrt 2, 1], are carried into the second stage's 8-point
+// transforms as ratios in the FMAs that replace their additions (the
+// scaled-twiddle method for fused multiply-add hardware of Linzer and Feig).
+// Every ratio has a magnitude between 1/2 and 2; the input of index 0 of each
+// second-stage transform is never twiddled, so its outputs carry no residual
+// scale.
+struct Tw {
+  int kind;       // 0: sigma * p with p = z; 1: p = i z; 2: p = -i z; 3: tangent; 4: cotangent
+  double sigma, t;
+};
+constexpr Tw tw64(int m) {
+  m = ((m % 64) + 64) % 64;
+  if (m == 0) return Tw{0, 1.0, 0.0};
+  if (m == 32) return Tw{0, -1.0, 0.0};
+  if (m == 16) return Tw{1, 1.0, 0.0};
+  if (m == 48) return Tw{2, 1.0, 0.0};
+  const double c = cos2pi(m, 64), s = sin2pi(m, 64);
+  const double ac = c < 0 ? -c : c, as = s < 0 ? -s : s;
+  if (ac >= as) return Tw{3, c, s / c};
+  return Tw{4, s, c / s};
+}
+
+// p such that w * z = sigma * p for w = exp(2 pi i m / 64)
+template <int M>
+__host__ __device__ __forceinline__ float2 tw_unit(float2 z) {
+  constexpr Tw w = tw64(M);
+  if constexpr (w.kind == 0) {
+    return z;
+  } else if constexpr (w.kind == 1) {
+    return make_float2(-z.y, z.x);
+  } else if constexpr (w.kind == 2) {
+    return make_float2(z.y, -z.x);
+  } else if constexpr (w.kind == 3) {
+    constexpr float t = float(w.t);
+    return make_float2(fmaf(-t, z.y, z.x), fmaf(t, z.x, z.y));
+  } else {
+    constexpr float k = float(w.t);
+    return make_float2(fmaf(k, z.x, -z.y), fmaf(k, z.y, z.x));
+  }
+}
+
+// a + r * b and a - r * b
+__host__ __device__ __forceinline__ void fma_pm(float2 a, float2 b, float r, float2& sum, float2& dif) {
+  sum = make_float2(fmaf(r, b.x, a.x), fmaf(r, b.y, a.y));
+  dif = make_float2(fmaf(-r, b.x, a.x), fmaf(-r, b.y, a.y));
+}
+
+template <int S>
+__host__ __device__ __forceinline__ float2 si_mul(float2 a) {   // (S i) * a
+  if constexpr (S > 0) return make_float2(-a.y, a.x);
+  else return make_float2(a.y, -a.x);
+}
+
+template <int S>
+__host__ __device__ __forceinline__ void fft64_scaled(float2* v) {
+  float2 p[8][8];   // [n2][k1]: first-stage outputs times the unit-diagonal twiddle factor
+  static_for<0, 8>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    float2 t[8];
+    static_for<0, 8>([&](auto n1c) { t[decltype(n1c)::value] = v[8 * decltype(n1c)::value + n2]; });
+    dft8<S>(t);
+    static_for<0, 8>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      p[n2][k1] = tw_unit<S * n2 * k1>(t[k1]);
+    });
+  });
+  static_for<0, 8>([&](auto k1c) {
+    constexpr int k1 = decltype(k1c)::value;
+    constexpr double sg[8] = {tw64(0).sigma,          tw64(S * 1 * k1).sigma, tw64(S * 2 * k1).sigma,
+                              tw64(S * 3 * k1).sigma, tw64(S * 4 * k1).sigma, tw64(S * 5 * k1).sigma,
+                              tw64(S * 6 * k1).sigma, tw64(S * 7 * k1).sigma};
+    // level 1: pairs (a, a + 4), scale sg[a]
+    float2 sp[4], dp[4];
+    static_for<0, 4>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      fma_pm(p[a][k1], p[a + 4][k1], float(sg[a + 4] / sg[a]), sp[a], dp[a]);
+    });
+    // level 2: the even (0, 2; scale sg[0] = 1) and odd (1, 3; scale sg[1]) 4-point transforms
+    float2 E[4], O[4];
+    fma_pm(sp[0], sp[2], float(sg[2] / sg[0]), E[0], E[2]);
+    fma_pm(dp[0], si_mul<S>(dp[2]), float(sg[2] / sg[0]), E[1], E[3]);
+    fma_pm(sp[1], sp[3], float(sg[3] / sg[1]), O[0], O[2]);
+    fma_pm(dp[1], si_mul<S>(dp[3]), float(sg[3] / sg[1]), O[1], O[3]);
+    // level 3: X[k] = E[k] +- w8^(S k) sg[1] O[k]
+    constexpr float r1 = float(sg[1] / sg[0]);
+    constexpr float r1h = float(sg[1] / sg[0] * 0.70710678118654752440);
+    float2 X[8];
+    fma_pm(E[0], O[0], r1, X[0], X[4]);
+    fma_pm(E[1], make_float2(O[1].x - S * O[1].y, O[1].y + S * O[1].x), r1h, X[1], X[5]);
+    fma_pm(E[2], si_mul<S>(O[2]), r1, X[2], X[6]);
+    fma_pm(E[3], make_float2(-O[3].x - S * O[3].y, S * O[3].x - O[3].y), r1h, X[3], X[7]);
+    static_for<0, 8>([&](auto k2c) { v[k1 + 8 * decltype(k2c)::value] = X[decltype(k2c)::value]; });
+  });
+}
+
 // In-register FFT of one pencil of N <= 64 values.
 // N = R1 * R2, n = R2 n1 + n2, k = k1 + R1 k2:
 //   X[k1 + R1 k2] = sum_n2 w_R2^(n2 k2) w_N^(n2 k1) [sum_n1 x[R2 n1 + n2] w_R1^(n1 k1)]
+// (64 points: fft64_scaled, the same split with the twiddles in FMAs).
 template <int N, int S>
-__device__ __forceinline__ void fft_reg(float2* v) {
-  if constexpr (N <= 8) {
+__host__ __device__ __forceinline__ void fft_reg(float2* v) {
+  if constexpr (N == 64) {
+    fft64_scaled<S>(v);
+  } else if constexpr (N <= 8) {
     dft_small<N, S>(v);
   } else {
     constexpr int R1 = FftSplit<N>::R1, R2 = FftSplit<N>::R2;

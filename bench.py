@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0",
-            "fetch_kib": 175057.6, "fetch_scale": 2.000, "write_kib": 61440.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0",
-                      "fetch_kib": 174342.5, "fetch_scale": 2.000, "write_kib": 20480090.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0",
+            "fetch_kib": 175067.8, "fetch_scale": 2.000, "write_kib": 65536.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0",
+                      "fetch_kib": 174854.8, "fetch_scale": 2.000, "write_kib": 20493396.5, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "50898b7f4d83a4d4d0dac50c34680ea761faa1dd81c0ff1916007edaa9c5cda0", "valu_issue_frac": 0.60, "lds_busy_frac": 0.52},
+    "lwa": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0", "valu_issue_frac": 0.57, "lds_busy_frac": 0.54},
 }
 
 

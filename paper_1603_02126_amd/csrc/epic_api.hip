@@ -678,11 +678,15 @@ int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0, bo
   if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
   if (fused) {
     // the fused run pulls items dynamically, solve workgroups joining late:
-    // twice the items of the separate launch keep the last ones short
-    // (LWA shape: 16 splits 6.20 ms, 32 splits 6.07 ms per fused launch)
+    // half again the items of the separate launch keep the last ones short,
+    // in whole rounds over the CUs (LWA shape, per fused launch: 16 splits
+    // 5.16 ms, 20: 5.07, 24: 5.02-5.07, 28: 5.14, 32: 5.17, 48: 5.18)
     const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
-    const int64_t s2 = 2 * int64_t(pick_splits(p, ap, T, 0, false));
-    return int(std::max<int64_t>(1, std::min<int64_t>(s2, std::max<int64_t>(1, T / per_split))));
+    const int64_t units = int64_t(F) * units_for(ap);
+    int64_t sf = (3 * int64_t(pick_splits(p, ap, T, 0, false)) + 1) / 2;
+    const int64_t rounds = (units * sf + p->n_cu - 1) / p->n_cu;
+    sf = (rounds * p->n_cu + units - 1) / units;
+    return int(std::max<int64_t>(1, std::min<int64_t>(sf, std::max<int64_t>(1, T / per_split))));
   }
   // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames
   // per slot; at 64 x 64 (the two-waves-per-SIMD engines: eight waves) >= 16

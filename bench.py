@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0",
-            "fetch_kib": 175067.8, "fetch_scale": 2.000, "write_kib": 65536.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0",
-                      "fetch_kib": 174854.8, "fetch_scale": 2.000, "write_kib": 20493396.5, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81",
+            "fetch_kib": 175064.3, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81",
+                      "fetch_kib": 174341.0, "fetch_scale": 2.000, "write_kib": 20480082.8, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "f2a97d9e436f7f1880fbcc2704399edd724e5a7fb9b3c18b8345d2088711a6b0", "valu_issue_frac": 0.57, "lds_busy_frac": 0.54},
+    "lwa": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81", "valu_issue_frac": 0.57, "lds_busy_frac": 0.53},
 }
 
 

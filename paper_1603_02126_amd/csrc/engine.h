@@ -196,6 +196,12 @@ __device__ __forceinline__ void stage_frame(float2* epr, const Raw (&raw)[APL], 
 template <int B = 4>
 __device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const uint2* stab, int S, int L,
                                            int lam) {
+  // the table addresses come from an opaque copy of the lane index: hoisted
+  // out of a frame loop as invariants (one per slot) they took registers the
+  // FFTs need and were spilled
+  int lo = lam;
+  asm volatile("" : "+v"(lo));
+  const uint2* col = stab + lo;
   float2 acc = make_float2(0.f, 0.f);
   for (int s0 = 0; s0 < S; s0 += B) {
     uint2 e[B];
@@ -203,7 +209,7 @@ __device__ __forceinline__ void grid_frame(float2* buf, const float2* epr, const
     static_for<0, B>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int s = s0 + k < S ? s0 + k : S - 1;
-      e[k] = stab[s * L + lam];
+      e[k] = col[s * L];
     });
     static_for<0, B>([&](auto kc) { ev[decltype(kc)::value] = epr[e[decltype(kc)::value].x & kSlotAntMask]; });
     static_for<0, B>([&](auto kc) {

@@ -198,13 +198,16 @@ template <int R, int B>
 __device__ __forceinline__ void grid_cls_half(float2* H, const float2* epr, const float2* tw, const uint2* stab,
                                               int S, int hf, int cx, int cy, int lam) {
   constexpr int N = 64 * R;
+  int lo = lam;                 // opaque copy: no per-slot table address held across the frame loop
+  asm volatile("" : "+v"(lo));
+  const uint2* col = stab + lo;
   float2 sum = make_float2(0.f, 0.f);
   for (int s0 = 0; s0 < S; s0 += B) {
     uint2 e[B];
     float2 ev[B], ph[B];
     static_for<0, B>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      e[k] = stab[(s0 + k < S ? s0 + k : S - 1) * 64 + lam];
+      e[k] = col[(s0 + k < S ? s0 + k : S - 1) * 64];
     });
     static_for<0, B>([&](auto kc) {
       constexpr int k = decltype(kc)::value;

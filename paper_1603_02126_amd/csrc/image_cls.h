@@ -399,10 +399,13 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
   static_for<0, NCY>([&](auto jc) {
     static_for<0, R>([&](auto mc) { acc[decltype(jc)::value][decltype(mc)::value] = make_float2(0.f, 0.f); });
   });
+  int ow = owner;               // opaque copy: no per-slot table address held across the frame loop
+  asm volatile("" : "+v"(ow));
+  tab += ow;
   uint2 nxt[B];
   static_for<0, B>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    nxt[k] = gload(tab + (k < S ? k : S - 1) * OW + owner);
+    nxt[k] = gload(tab + (k < S ? k : S - 1) * OW);
   });
   for (int s0 = 0; s0 < S; s0 += B) {
     uint2 e[B];
@@ -410,7 +413,7 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
     if (s0 + B < S) {
       static_for<0, B>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        nxt[k] = gload(tab + (s0 + B + k < S ? s0 + B + k : S - 1) * OW + owner);
+        nxt[k] = gload(tab + (s0 + B + k < S ? s0 + B + k : S - 1) * OW);
       });
     }
     static_for<0, B>([&](auto kc) {

@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81",
-            "fetch_kib": 175064.3, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81",
-                      "fetch_kib": 174341.0, "fetch_scale": 2.000, "write_kib": 20480082.8, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53",
+            "fetch_kib": 175064.5, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53",
+                      "fetch_kib": 174341.1, "fetch_scale": 2.000, "write_kib": 20480081.4, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "8cb56b5406b472384ee61fec0f769bf9946d8f1f1f7f5ab789962ef4d5c67f81", "valu_issue_frac": 0.57, "lds_busy_frac": 0.53},
+    "lwa": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53", "valu_issue_frac": 0.57, "lds_busy_frac": 0.53},
 }
 
 

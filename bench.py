@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53",
-            "fetch_kib": 175064.5, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53",
-                      "fetch_kib": 174341.1, "fetch_scale": 2.000, "write_kib": 20480081.4, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6",
+            "fetch_kib": 175061.0, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6",
+                      "fetch_kib": 174335.1, "fetch_scale": 2.000, "write_kib": 20480083.5, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "94f3cd85876e371f5ec0c72306a5c3148b3f53f5d3811f9491ea2d25a4f8da53", "valu_issue_frac": 0.57, "lds_busy_frac": 0.53},
+    "lwa": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
 }
 
 

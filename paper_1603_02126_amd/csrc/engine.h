@@ -161,10 +161,6 @@ __device__ __forceinline__ float2 lds_take(float2* p) {
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   return make_float2(__uint_as_float(uint32_t(r)), __uint_as_float(uint32_t(r >> 32)));
 }
-__device__ __forceinline__ float lds_take(float* p) {
-  return __uint_as_float(__hip_atomic_exchange(reinterpret_cast<unsigned*>(p), 0u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WAVEFRONT));
-}
 
 template <int X0>
 __device__ __forceinline__ void take_half_row(float2 (&v)[64], float2* H, int lam) {

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjointArgs a) {
 // The same adjoint with two waves per SIMD (64 x 64, integer E-fields, 129..256
 // antennas), built like the paired imaging engine: eight waves per
 // workgroup, each imaging its own frames through half a frame (columns 0..31,
-// then 32..63) and transposing in registers.  After R and the conjugate
+// then 32..63) and transposing through that half buffer (xpose.h).  After R and the conjugate
 // transform the frame G' (lane = row y) goes back through the same half
 // buffer, one half of the columns at a time, and each lane gathers its
 // antennas' kernel cells of that half (the other half's cells carry weight

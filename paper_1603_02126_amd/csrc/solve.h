@@ -407,13 +407,17 @@ __device__ __forceinline__ void solve_channel_wave(const SolveArgs& a, int f, fl
   const int64_t rowstride = int64_t(a.F) * a.Na * bpe;
   const uint8_t* ebase = a.efield + int64_t(f) * a.Na * bpe;
   const int64_t ia = int64_t(f) * a.Na + (own ? lane : 0);
-  double2 g = make_double2(0.0, 0.0), A = g, D = g;
+  // the constants folded as in solve_channel_fmt (epical_step_r): invD once,
+  // one real division per update for r = 1 / (Na |g|^2)
+  double2 g = make_double2(0.0, 0.0), A = g, invD = g;
   uint8_t hold = 0;
   uint32_t st = 0u;
   if (own) {
     g = a.gains[ia];
     A = a.A[ia];
-    D = a.D[ia];
+    const double2 D = a.D[ia];
+    const double d2 = D.x * D.x + D.y * D.y;
+    invD = make_double2(a.na_eff * D.x / d2, -a.na_eff * D.y / d2);
     hold = a.hold[ia];
     a.g_hist[ia] = g;
   }
@@ -428,11 +432,12 @@ __device__ __forceinline__ void solve_channel_wave(const SolveArgs& a, int f, fl
   };
   request(0);
   double2 c = make_double2(0.0, 0.0);
+  double rr = 0.0;
+  // c_a = A_a u_a / Na = A_a conj(g_a) r_a (zero for flagged antennas and idle lanes)
   auto coefficient = [&]() {
-    double2 u = zrecip(g);
-    if (!own || (hold & kHoldFlagged)) u = make_double2(0.0, 0.0);
-    const double2 cc = zmul(A, u);
-    c = make_double2(cc.x / a.na_eff, cc.y / a.na_eff);
+    rr = 1.0 / (a.na_eff * (g.x * g.x + g.y * g.y));
+    c = zmul(A, make_double2(g.x * rr, -g.y * rr));
+    if (!own || (hold & kHoldFlagged)) c = make_double2(0.0, 0.0);
   };
   coefficient();
   double kx = 0.0, ky = 0.0, q = 0.0;
@@ -455,7 +460,7 @@ __device__ __forceinline__ void solve_channel_wave(const SolveArgs& a, int f, fl
     q = fma(ex, ex, fma(ey, ey, q));
     if (t + 1 == t_end) {
       const double inv_n = 1.0 / double(t_end - int64_t(n) * a.t_cal);
-      g = epical_step(make_double2(kx * inv_n, ky * inv_n), q * inv_n, A, D, g, hold, a.na_eff, a.gamma, &st);
+      g = epical_step_r(make_double2(kx * inv_n, ky * inv_n), q * inv_n, A, invD, g, rr, hold, a.gamma, &st);
       if (own) a.g_hist[(int64_t(n + 1) * a.F + f) * a.Na + lane] = g;
       kx = ky = q = 0.0;
       ++n;

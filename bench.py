@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # any change to one of them makes the figure stale and it is reported as null.
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6",
-            "fetch_kib": 175061.0, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6",
-                      "fetch_kib": 174335.1, "fetch_scale": 2.000, "write_kib": 20480083.5, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3",
+            "fetch_kib": 175061.1, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3",
+                      "fetch_kib": 174335.2, "fetch_scale": 2.000, "write_kib": 20480083.0, "write_scale": 1.000},
 }
 
 
@@ -64,7 +64,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "f0e77c7ab3a143b3fac5b9e68cbfa0c80c16ea9017195fea42455b3c579225c6", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
 }
 
 

@@ -353,7 +353,8 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
 //   z exp(+2 pi i jy cy / N) exp(+2 pi i jx cx / N)
 // into the owner's register sums, which go to the classes' half frames when
 // the sub-cell's last contribution has been added.  One table entry, one E'
-// and five twiddles serve eight classes (R = 4), against one table entry, one
+// and three twiddle loads (the column twiddles' higher powers are products)
+// serve eight classes (R = 4), against one table entry, one
 // E' and one twiddle per contribution and class when each wave grids its own
 // class.  Each wave then takes its class's half rows, runs the row FFTs,
 // transposes through the half frame and runs the column FFTs, as the paired engines do.
@@ -423,9 +424,11 @@ __device__ __forceinline__ void grid_dense_half(float2* H0, const float2* epr, c
       const int jx = qx + 64 * int((code >> 24) & 3), jy = qy + 64 * int((code >> 26) & 3);
       const float2 ev = epr[code & kSlotAntMask];
       float2 tx[R], ty[NCY];
-      static_for<1, R>([&](auto mc) {
+      // tx[m] = e^{+2 pi i jx m / N}: one gather, the higher powers by products
+      tx[1] = tw[jx & (N - 1)];
+      static_for<2, R>([&](auto mc) {
         constexpr int m = decltype(mc)::value;
-        tx[m] = tw[(jx * m) & (N - 1)];
+        tx[m] = cmul(tx[m - 1], tx[1]);
       });
       static_for<0, NCY>([&](auto jc) {
         constexpr int j = decltype(jc)::value;

@@ -47,14 +47,16 @@ PEAK_HBM_GBS = 8000.0
 # and snapshot forms), from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
 # per dispatch), each scaled by what the same counter reads for a plain 256 MiB
 # device copy (FETCH x2.000, WRITE x1.000).  Valid only for the sources that
-# determine the imaging kernels' code, as they were when the counters were taken:
+# determine the imaging kernels' code and their launch configuration (the time
+# splits, chosen in epic_api.hip), as they were when the counters were taken:
 # any change to one of them makes the figure stale and it is reported as null.
-TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h")
+TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h",
+                   "epic_api.hip")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3",
-            "fetch_kib": 175061.1, "fetch_scale": 2.000, "write_kib": 32768.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3",
-                      "fetch_kib": 174335.2, "fetch_scale": 2.000, "write_kib": 20480083.0, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "0f29f647a163d75a6727fed88d6422715b5ad7b0071e2f91762a18804ba1cb96",
+            "fetch_kib": 173449.3, "fetch_scale": 2.000, "write_kib": 8192.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "0f29f647a163d75a6727fed88d6422715b5ad7b0071e2f91762a18804ba1cb96",
+                      "fetch_kib": 174334.7, "fetch_scale": 2.000, "write_kib": 20480073.3, "write_scale": 1.000},
 }
 
 
@@ -64,7 +66,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "d61b2aabe4af268632c1c5d8fdf92a0adb8759cfcbc7d5600f7b7fb3612bc0d3", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "0f29f647a163d75a6727fed88d6422715b5ad7b0071e2f91762a18804ba1cb96", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
 }
 
 

@@ -256,8 +256,9 @@ int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
  *                        caller's stream by events) and replays it while the
  *                        buffers and n_samples stay the same.
  *   EPIC_OPT_OVERLAP     1 (default) = where every array of the plan allows it
- *                        (one tapped pixel, no band, more than 64 antennas or
- *                        intervals longer than 8 samples, an imaging engine of
+ *                        (no band; one tapped pixel with more than 64 antennas
+ *                        or intervals longer than 8 samples, or several tapped
+ *                        pixels with at most 512 antennas; an imaging engine of
  *                        the persistent kernel, the FFT transform) and the
  *                        plan's channels number fewer than the GPU's CUs (the
  *                        solve, one workgroup per channel, leaves CUs idle),
@@ -267,9 +268,10 @@ int epical_set_denominator(epic_plan_t plan, int32_t array, const double* D);
  *                        the imaging of a time split starts once its intervals
  *                        are published, so that the imaging runs on the CUs the
  *                        solve leaves free; results equal the separate launches'
- *                        (gains bit for bit, images within rounding).  Timing
- *                        then counts the one launch as imaging.  0 = separate
- *                        launches.  epic_run_noalloc never fuses. */
+ *                        (with one pixel gains bit for bit, with several the
+ *                        same sums in another order; images within rounding).
+ *                        Timing then counts the one launch as imaging.
+ *                        0 = separate launches.  epic_run_noalloc never fuses. */
 #define EPIC_OPT_SPLITS 1
 #define EPIC_OPT_TRANSFORM 2
 #define EPIC_OPT_TIMING 3

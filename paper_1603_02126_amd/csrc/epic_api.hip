@@ -672,36 +672,55 @@ int units_for(const ArrayPlan& ap) { return epic::cls_groups(engine_probe(ap), a
 // Frames a workgroup images at once.
 int slots_for(int N) { return N >= 128 ? 1 : 4 * (64 / N); }
 
-int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0, bool fused = false) {
-  const int F = ap.h.F, N = ap.h.nx;
-  if (tuned > 0) return int(std::max<int64_t>(1, std::min<int64_t>(tuned, std::max<int64_t>(1, T))));
-  if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
-  if (fused) {
-    // the fused run pulls items dynamically, solve workgroups joining late:
-    // half again the items of the separate launch keep the last ones short,
-    // in whole rounds over the CUs (LWA shape, per fused launch: 16 splits
-    // 5.16 ms, 20: 5.07, 24: 5.02-5.07, 28: 5.14, 32: 5.17, 48: 5.18)
-    const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
-    const int64_t units = int64_t(F) * units_for(ap);
-    int64_t sf = (3 * int64_t(pick_splits(p, ap, T, 0, false)) + 1) / 2;
-    const int64_t rounds = (units * sf + p->n_cu - 1) / p->n_cu;
-    sf = (rounds * p->n_cu + units - 1) / units;
-    return int(std::max<int64_t>(1, std::min<int64_t>(sf, std::max<int64_t>(1, T / per_split))));
-  }
-  // aim for >= 2048 workgroups (8 per CU on 256 CUs) while keeping >= 8 frames
-  // per slot; at 64 x 64 (the two-waves-per-SIMD engines: eight waves) >= 16
-  // frames per wave, which repays a workgroup's set-up and reduction (the
-  // 1000-sample differentiable workload: 31 splits 1.20 ms, 8 splits 1.08 ms)
-  const int64_t units = int64_t(F) * units_for(ap);
-  int64_t s = (2048 + units - 1) / units;
+// What a time-split count is for: the separate imaging launch of a run or of
+// the stage-wise call, the fused solve + imaging launch, or another kernel
+// (snapshots, the adjoint, the autotuner's reference point).
+enum class SplitUse { image, fused, other };
+
+// Time splits per channel for a target of `wg` workgroups, keeping >= 8 frames
+// per slot; at 64 x 64 (the two-waves-per-SIMD engines: eight waves) >= 16
+// frames per wave, which repays a workgroup's set-up and reduction (the
+// 1000-sample differentiable workload: 31 splits 1.20 ms, 8 splits 1.08 ms),
+// rounded up to whole rounds of workgroups over the CUs (one imaging
+// workgroup per CU).
+int64_t splits_for_target(epic_plan_t p, const ArrayPlan& ap, int64_t T, int64_t wg) {
+  const int N = ap.h.nx;
+  const int64_t units = int64_t(ap.h.F) * units_for(ap);
+  int64_t s = (wg + units - 1) / units;
   const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
   s = std::min<int64_t>(s, std::max<int64_t>(1, T / per_split));
-  // whole rounds of workgroups over the CUs (one imaging workgroup per CU)
   if (units * s > p->n_cu) {
     const int64_t rounds = (units * s + p->n_cu - 1) / p->n_cu;
     s = std::min<int64_t>((rounds * p->n_cu + units - 1) / units, std::max<int64_t>(1, T));
   }
-  return int(std::max<int64_t>(1, s));
+  return std::max<int64_t>(1, s);
+}
+
+int pick_splits(epic_plan_t p, const ArrayPlan& ap, int64_t T, int tuned = 0, SplitUse use = SplitUse::other) {
+  const int N = ap.h.nx;
+  if (tuned > 0) return int(std::max<int64_t>(1, std::min<int64_t>(tuned, std::max<int64_t>(1, T))));
+  if (p->splits > 0) return int(std::max<int64_t>(1, std::min<int64_t>(p->splits, std::max<int64_t>(1, T))));
+  if (use == SplitUse::fused) {
+    // the fused run pulls items dynamically, solve workgroups joining late:
+    // half again the items of 2048 workgroups keep the last ones short, in
+    // whole rounds over the CUs (LWA shape, per fused launch: 16 splits
+    // 5.16 ms, 20: 5.07, 24: 5.02-5.07, 28: 5.14, 32: 5.17, 48: 5.18)
+    const int64_t per_split = N == 64 ? 8 * 16 : 8 * int64_t(slots_for(N));
+    const int64_t units = int64_t(ap.h.F) * units_for(ap);
+    int64_t sf = (3 * splits_for_target(p, ap, T, 2048) + 1) / 2;
+    const int64_t rounds = (units * sf + p->n_cu - 1) / p->n_cu;
+    sf = (rounds * p->n_cu + units - 1) / units;
+    return int(std::max<int64_t>(1, std::min<int64_t>(sf, std::max<int64_t>(1, T / per_split))));
+  }
+  // the separate launch of the paired 64 x 64 engine: every workgroup images
+  // the same number of frames, so two rounds over the CUs balance as well as
+  // eight and set up and reduce a quarter as often (LWA shape, per launch:
+  // 16 splits 4.38-4.44 ms, 8: 4.33, 4: 4.31-4.34, 2: 4.27-4.31; 3, one and a
+  // half rounds: 5.78); the partial images written drop from 33.6 to 8.4 MB
+  if (use == SplitUse::image && N == 64 && epic::pair_engine(engine_probe(ap), N))
+    return int(splits_for_target(p, ap, T, 2 * int64_t(p->n_cu)));
+  // aim for >= 2048 workgroups (8 per CU on 256 CUs)
+  return int(splits_for_target(p, ap, T, 2048));
 }
 
 }  // namespace
@@ -1257,9 +1276,9 @@ static int body_of(epic_plan_t plan, const ArrayPlan& ap) {
 static bool own_launch(epic_plan_t plan, const ArrayPlan& ap) { return body_of(plan, ap) == 0; }
 
 // The fused run (one launch for the solve and the imaging) applies when every
-// array takes the single-pixel solve of kSolveMainThreads threads (no band,
-// one tapped pixel, not the one-wave solve of tiny arrays) and is imaged by a
-// body of the persistent kernel, and pays when the separate solve launch
+// array's solve runs at kSolveMainThreads threads (no band; one tapped pixel,
+// not the one-wave solve of tiny arrays, or several pixels with at most
+// kSolveMainThreads antennas) and is imaged by a body of the persistent kernel, and pays when the separate solve launch
 // would leave CUs idle: fewer solve tasks (channels of all arrays) than CUs.
 // With more, the solve fills the chip by itself and the fused run only adds
 // the cost of finer imaging items (HERA shape, 512 channels: 23.0 against
@@ -1270,7 +1289,11 @@ static bool fused_eligible(epic_plan_t plan) {
   for (const ArrayPlan& ap : plan->arrays) n_chan += ap.h.F;
   if (n_chan >= plan->n_cu) return false;
   for (const ArrayPlan& ap : plan->arrays) {
-    if (ap.band_mode != EPIC_BAND_NONE || ap.n_pix != 1 || own_launch(plan, ap)) return false;
+    if (ap.band_mode != EPIC_BAND_NONE || own_launch(plan, ap)) return false;
+    if (ap.n_pix > 1) {
+      if (!epic::solve_multi_fusable(ap.h.na, ap.h.efmt)) return false;
+      continue;
+    }
     epic::SolveArgs probe{};
     probe.Na = ap.h.na;
     probe.n_pix = 1;
@@ -1428,8 +1451,10 @@ static int enqueue_fused(epic_plan_t plan, const std::vector<RunLayout>& lay, ch
                           ap.t_cal, reinterpret_cast<float*>(scr + lay[i].p_off), lay[i].splits);
     b.code[i] = body_of(plan, ap);
     const epic::SolveArgs& a = sa[i];
+    const int code = ap.n_pix > 1 ? epic::kFusedMultiCode + solve_ps(ap.h)
+                                  : 100 * epic::solve_main_j(ap.h.na) + solve_ps(ap.h);
     fa.sx[i] = epic::FusedSolveExtra{a.A, a.D, a.hold, a.gains, a.g_hist, a.status, a.na_eff, a.gamma, a.n_int,
-                                     100 * epic::solve_main_j(ap.h.na) + solve_ps(ap.h)};
+                                     code, ap.n_pix};
     fa.chan_off[i + 1] = fa.chan_off[i] + ap.h.F;
   }
   fa.n_solve = fa.chan_off[na_arr];
@@ -1568,8 +1593,8 @@ static int prepare_run(epic_plan_t plan, const void* const* efield, int64_t n_sa
                              {gain_hist ? gain_hist[i] : nullptr, "gain_hist"},
                              {ant_status ? ant_status[i] : nullptr, "ant_status"}})))
       return rc;
-    const int sp = splits && (*splits)[i] > 0 ? (*splits)[i]
-                                                : pick_splits(plan, ap, n_samples, ap.tune_splits, fused);
+    const SplitUse use = fused ? SplitUse::fused : SplitUse::image;
+    const int sp = splits && (*splits)[i] > 0 ? (*splits)[i] : pick_splits(plan, ap, n_samples, ap.tune_splits, use);
     rc = layout_array(ap, n_samples, sp, size_t(ap.h.F) * ap.h.nx * ap.h.ny, lay[i], need, any_band);
     if (rc) return rc;
   }
@@ -1781,7 +1806,7 @@ int epic_image(epic_plan_t plan, int32_t array, const void* efield, int64_t n_sa
   if ((rc = check_aligned({{efield, "efield"}, {gains, "gains"}, {image, "image"}}))) return rc;
   if (ap.h.na_eff < 1) return fail(EPIC_ERR_ARG, "all antennas are flagged");
   const HostArray& h = ap.h;
-  const int splits = pick_splits(plan, ap, n_samples, ap.tune_splits);
+  const int splits = pick_splits(plan, ap, n_samples, ap.tune_splits, SplitUse::image);
   const size_t ub = ((size_t(h.F) * h.na * sizeof(float2) + 255) / 256) * 256;
   void* scr = nullptr;
   rc = plan_scratch(plan, ub + size_t(splits) * h.F * h.nx * h.ny * sizeof(float), &scr);

@@ -194,8 +194,10 @@ struct FusedSolveExtra {
   uint32_t* status;
   double na_eff, gamma;
   int n_int;
-  int code;                 // 100 J + PS of the single-pixel solve body
+  int code;                 // 100 J + PS of the single-pixel solve body, kFusedMultiCode + PS with several pixels
+  int n_pix;                // tapped pixels
 };
+constexpr int kFusedMultiCode = 1000;
 
 struct FusedArgs {
   FusedSolveExtra sx[kMaxBatch];
@@ -261,6 +263,8 @@ hipError_t launch_image_acc(int N, const ImageAccArgs& a, hipStream_t s);
 hipError_t launch_reduce(const float* partial, int splits, int64_t per_split, double scale,
                          float* image, hipStream_t s);
 bool solve_supported(int na, int fmt, int n_pix = 1);
+// the several-pixel solve runs as a task of the fused run (kSolveMainThreads threads)
+bool solve_multi_fusable(int na, int fmt);
 int solve_main_j(int na);   // antennas per thread slot of the single-pixel solve
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 // The solve of these arrays runs one wave per channel (small arrays, short

@@ -8,9 +8,9 @@ namespace epic {
 // ---------------------------------------------------------------------------
 // Fused run: the calibration solve and the imaging of every array in one
 // launch (FusedArgs).  The first workgroups to start take the solve tasks
-// (tickets 0 .. n_solve-1, one channel each, the single-pixel solve at
-// kSolveMainThreads = kBatchThreads threads publishing u interval by
-// interval); a workgroup whose ticket is past the solve tasks pulls imaging
+// (tickets 0 .. n_solve-1, one channel each, the single-pixel or the
+// several-pixel solve at kSolveMainThreads = kBatchThreads threads publishing
+// u interval by interval); a workgroup whose ticket is past the solve tasks pulls imaging
 // items and, before each, waits until the channel has published every
 // interval its samples fall in.  Tickets are taken by running workgroups
 // only, so every solve a wait depends on is already running; the solves
@@ -43,8 +43,21 @@ __device__ __noinline__ void fused_solve_call(const SolveArgs& a, int f, uint8_t
   else solve_channel_fmt<J, PS, kCF32, kSolveMainThreads, true>(la, f, smem, progress);
 }
 
+// Several tapped pixels (arrays of at most kSolveMainThreads antennas).
+template <int PS>
+__device__ __noinline__ void fused_multi_call(const SolveArgs& a, int f, uint8_t* smem, int* progress) {
+  const SolveArgs la = uniform_copy(a);
+  f = __builtin_amdgcn_readfirstlane(f);
+  if (la.fmt == kCI4) solve_channel_multi<PS, kCI4, kSolveMainThreads, true>(la, f, smem, progress);
+  else if (la.fmt == kCI8) solve_channel_multi<PS, kCI8, kSolveMainThreads, true>(la, f, smem, progress);
+  else solve_channel_multi<PS, kCF32, kSolveMainThreads, true>(la, f, smem, progress);
+}
+
 __device__ __forceinline__ void run_solve(int code, const SolveArgs& a, int f, uint8_t* smem, int* progress) {
   switch (code) {
+    case kFusedMultiCode + 16: fused_multi_call<16>(a, f, smem, progress); break;
+    case kFusedMultiCode + 4: fused_multi_call<4>(a, f, smem, progress); break;
+    case kFusedMultiCode + 1: fused_multi_call<1>(a, f, smem, progress); break;
     case 116: fused_solve_call<1, 16>(a, f, smem, progress); break;
     case 104: fused_solve_call<1, 4>(a, f, smem, progress); break;
     case 101: fused_solve_call<1, 1>(a, f, smem, progress); break;
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_run_fused(BatchImageArgs b, F
       sa.u_hist = const_cast<float2*>(ia.u);
       sa.g_hist = x.g_hist;
       sa.status = x.status;
-      sa.n_pix = 1;
+      sa.n_pix = x.n_pix;
       __builtin_memcpy(item_raw, &sa, sizeof(SolveArgs));
     }
     __syncthreads();

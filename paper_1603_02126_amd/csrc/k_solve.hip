@@ -86,6 +86,11 @@ bool solve_supported(int na, int fmt, int n_pix) {
   return na <= 4 * kSolveMainThreads && RB <= stage_cap<8, kSolveMainThreads>(RB);
 }
 
+bool solve_multi_fusable(int na, int fmt) {
+  const int RB = na * efmt_bytes(fmt);
+  return na >= 1 && na <= kSolveMainThreads && RB <= stage_cap<8, kSolveMainThreads>(RB);
+}
+
 template <int J>
 static hipError_t launch_solve_j(const SolveArgs& a, hipStream_t s) {
   const int RB = a.Na * efmt_bytes(a.fmt);

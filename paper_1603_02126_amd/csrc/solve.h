@@ -478,11 +478,16 @@ __device__ __forceinline__ void solve_channel_wave(const SolveArgs& a, int f, fl
 // EPICal from several tapped pixels (the multiple-pixel extension of Sec. 6):
 // per interval the taps P_p(t) = sum_a c_pa E_a(t) of every pixel, the
 // correlations K_ap = <E_a P_p*>, and the least-squares update over the
-// pixels (epical_step_multi).  Na <= kSolveThreads, at most kMaxPix pixels;
-// the loops over pixels are unrolled to kMaxPix with guards.
+// pixels (epical_step_multi).  Na <= T, at most kMaxPix pixels; the loops
+// over pixels are unrolled to kMaxPix with guards.  T threads (kSolveThreads
+// in its own launch, kSolveMainThreads as a task of the fused run); PUBLISH
+// as in the single-pixel solve: u = 1/g of every antenna is written to
+// a.u_hist at the start of each interval and progress[f] raised once every
+// wave's stores have completed.
 // ---------------------------------------------------------------------------
-template <int PS, int FMT>
-__device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, uint8_t* smem) {
+template <int PS, int FMT, int T = kSolveThreads, bool PUBLISH = false>
+__device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, uint8_t* smem, int* progress = nullptr) {
+  static_assert(T <= kSolveThreads, "the coefficient table holds kSolveThreads antennas per pixel");
   uint8_t (*chunk)[kSolveChunkBytes] = reinterpret_cast<uint8_t (*)[kSolveChunkBytes]>(smem);
   double2* P_l = reinterpret_cast<double2*>(smem + SolveSmem::P_OFF);   // [kMaxPix][kSolveMultiRows]
   double2* c_l = reinterpret_cast<double2*>(smem + SolveSmem::C_OFF);   // [kMaxPix][kSolveThreads]
@@ -493,13 +498,13 @@ __device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, u
   const int64_t rowstride = int64_t(a.F) * RB;
   const int64_t pstride = int64_t(a.F) * a.Na;
   const uint8_t* ebase = a.efield + int64_t(f) * RB;
-  using Stage = Stager<PS, 8>;
+  using Stage = Stager<PS, 8, T>;
   int rpc = Stage::CAP / RB;
   rpc = rpc < kSolveMultiRows ? rpc : kSolveMultiRows;
 
   int NaP = 16;
-  while (NaP < a.Na && NaP < kSolveThreads) NaP <<= 1;
-  const int RG = kSolveThreads / NaP;
+  while (NaP < a.Na && NaP < T) NaP <<= 1;
+  const int RG = T / NaP;
   const int rg = tid % RG;
   const int an = tid / RG;
   const bool own = an < a.Na;
@@ -546,11 +551,22 @@ __device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, u
           const double2 c = zmul(A[p], u);
           c_l[p * kSolveThreads + an] = make_double2(c.x / a.na_eff, c.y / a.na_eff);
         }
+      if constexpr (PUBLISH) {
+        const float2 uf = make_float2(float(u.x), float(u.y));
+        __hip_atomic_store((__attribute__((address_space(1))) uint64_t*)(a.u_hist + (int64_t(n) * a.F + f) * a.Na + an),
+                           __builtin_bit_cast(uint64_t, uf), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
+    if constexpr (PUBLISH) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's u stores are done
     double Kx[kMaxPix], Ky[kMaxPix], Q = 0.0;
 #pragma unroll
     for (int p = 0; p < kMaxPix; ++p) Kx[p] = Ky[p] = 0.0;
     __syncthreads();
+    if constexpr (PUBLISH) {
+      if (tid == 0)
+        __hip_atomic_store((__attribute__((address_space(1))) int*)(progress + f), n + 1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
     for (int r0 = 0; r0 < len; r0 += rpc) {
       const int nr = min(rpc, len - r0);
       int n_nx = n, r_nx = r0 + nr;
@@ -565,7 +581,7 @@ __device__ __forceinline__ void solve_channel_multi(const SolveArgs& a, int f, u
       // taps of every pixel: 16 lanes per row, DPP sums within the 16-lane row
       {
         const int q = tid & 15, rr = tid >> 4;
-        for (int rb = 0; rb < nr; rb += kSolveThreads / 16) {
+        for (int rb = 0; rb < nr; rb += T / 16) {
           const int r = rb + rr;
           double px[kMaxPix], py[kMaxPix];
 #pragma unroll

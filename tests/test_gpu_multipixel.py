@@ -83,3 +83,57 @@ def test_stagewise_update_needs_one_pixel(cuda):
     with pytest.raises(lib.EpicError):
         plan.epical_update(0, e, 0, 10, tap, kq, g, finalize=True)
     plan.close()
+
+
+def _run_pixels(wl, packed, pix, overlap, dev):
+    from paper_1603_02126_amd import lib
+    plan = _plan(wl, pix)
+    plan.set_option(lib.OPT_OVERLAP, overlap)
+    plan.set_option(lib.OPT_TIMING, 1)
+    got = gpu_run(wl, packed, dev, plan=plan)
+    tim = plan.timing()
+    plan.close()
+    return got, tim
+
+
+@pytest.mark.parametrize("n,efmt,na,n_samples,t_cal,pix_idx", [
+    (64, synth.FMT_CI4, 200, 301, 100, [0, 2, 5]),        # paired engine, ragged last interval
+    (64, synth.FMT_CI8, 256, 250, 7, [0, 1, 2, 3]),       # four pixels, many short intervals
+    (128, synth.FMT_CI8, 512, 90, 40, [0, 4]),            # class-pair engine, the largest fused array
+    (32, synth.FMT_CF32, 90, 120, 30, [0, 3]),            # eight-wave FFT engine, complex float
+])
+def test_fused_several_pixels_match_oracle_and_separate_launches(cuda, n, efmt, na, n_samples, t_cal, pix_idx):
+    """Several tapped pixels in the fused run: the several-pixel solve runs as
+    a task of the persistent launch at 512 threads and publishes u interval by
+    interval.  Gains and images against the FP64 oracle, and the images
+    against the separate launches (whose solve sums the same terms at 1024
+    threads, in another order)."""
+    from paper_1603_02126_amd import lib
+    wl = synth.config_small(n=n, efmt=efmt, kernel=2, n_ant=na, n_chan=3, n_samples=n_samples, t_cal=t_cal)
+    packed = synth.make_efield(wl)
+    pix = wl.src_lmS[pix_idx, :2]
+    ref = _oracle_multi(wl, packed, pix)
+    fused, tf = _run_pixels(wl, packed, pix, 1, cuda)
+    sep, ts = _run_pixels(wl, packed, pix, 0, cuda)
+    assert tf[lib.TIMER_SOLVE][1] == 0 and tf[lib.TIMER_IMAGE][1] > 0     # one launch for both
+    assert ts[lib.TIMER_SOLVE][1] == 1
+    for got in (fused, sep):
+        assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+        assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+    assert gain_err(fused["hist"], sep["hist"]) <= 1e-8
+    assert image_err(fused["image"], sep["image"]).max() <= 1e-5
+
+
+def test_several_pixels_above_512_antennas_run_separately(cuda):
+    """Above 512 antennas the several-pixel solve needs its own 1024-thread
+    launch: the run keeps the separate launches with the fused option on and
+    still matches the oracle."""
+    from paper_1603_02126_amd import lib
+    wl = synth.config_small(n=128, efmt=synth.FMT_CI4, kernel=2, n_ant=600, n_chan=2, n_samples=60, t_cal=20)
+    packed = synth.make_efield(wl)
+    pix = wl.src_lmS[[0, 3], :2]
+    ref = _oracle_multi(wl, packed, pix)
+    got, tim = _run_pixels(wl, packed, pix, 1, cuda)
+    assert tim[lib.TIMER_SOLVE][1] == 1
+    assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
+    assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL

@@ -10,9 +10,9 @@ namespace epic {
 // launch (FusedArgs).  The first workgroups to start take the solve tasks
 // (tickets 0 .. n_solve-1, one channel each, the single-pixel or the
 // several-pixel solve at kSolveMainThreads = kBatchThreads threads publishing
-// u interval by interval); a workgroup whose ticket is past the solve tasks pulls imaging
-// items and, before each, waits until the channel has published every
-// interval its samples fall in.  Tickets are taken by running workgroups
+// u interval by interval); a workgroup whose ticket is past the solve tasks
+// pulls imaging items and, before each, waits until the channel has published
+// every interval its samples fall in.  Tickets are taken by running workgroups
 // only, so every solve a wait depends on is already running; the solves
 // themselves never wait.
 // ---------------------------------------------------------------------------

@@ -69,7 +69,16 @@ __host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__host__ __device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+// acc[i] += |v[i]|^2 for i < M, as two fused multiply-adds into each
+// accumulator (one instruction fewer per value than squaring into a sum)
+template <int M, int A, int V>
+__host__ __device__ __forceinline__ void add_norms(float (&acc)[A], const float2 (&v)[V]) {
+  static_assert(M <= A && M <= V, "accumulators and values for every index");
+  static_for<0, M>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    acc[i] = fmaf(v[i].y, v[i].y, fmaf(v[i].x, v[i].x, acc[i]));
+  });
+}
 
 // multiply by S*i
 template <int S>

@@ -147,7 +147,7 @@ __device__ __forceinline__ void image_cls_item(const ImageArgs& a, int f, int cg
     else wave_lds_sync();
     float2 v[64];
     transform_frame<64, +1>(buf, v, lane);
-    static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<64>(acc, v);
   }
   // class pixels: (R ky + cy, R kx + cx) with kx = lane
   float* out = a.partial + (int64_t(s) * a.F + f) * (int64_t(N) * N);
@@ -321,7 +321,7 @@ __device__ __forceinline__ void image_cls_pair_item(const ImageArgs& a, int f, i
     __builtin_amdgcn_s_setprio(0);
     fft_reg<NF, +1>(v);
     fetch_raw(t + 2);
-    static_for<0, NF>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<NF>(acc, v);
   }
   // sum the two frame slots of each class, then write the class pixels
   // (R y + cy, R kx + cx) with kx = lam
@@ -531,7 +531,7 @@ __device__ __forceinline__ void image_cls_dense_item(const ImageArgs& a, int f, 
     transpose64(v, H, lam);
     fft_reg<64, +1>(v);
     fetch_raw(t + NF);
-    static_for<0, 64>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<64>(acc, v);
   }
   // class pixels (R y + cy, R kx + cx), kx = lam; at R = 2 the two frame
   // slots of each class are summed first

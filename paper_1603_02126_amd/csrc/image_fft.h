@@ -56,7 +56,7 @@ __device__ __forceinline__ void image_item(const ImageArgs& a, int f, int s, uin
     wave_lds_sync();
     float2 v[N];
     transform_frame<N, +1>(buf, v, lam);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<N>(acc, v);
   }
 
   // workgroup reduction of the SLOTS accumulators
@@ -173,7 +173,7 @@ __device__ __forceinline__ void pair_frames(const ImageArgs& a, int f, int64_t t
     // the next frame's samples are requested here rather than at staging:
     // their registers would otherwise stay live through both FFTs
     fetch_raw(t + INFLIGHT);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<N>(acc, v);
   }
 }
 
@@ -307,7 +307,7 @@ __device__ __forceinline__ void image_item_snap(const ImageArgs& a, int f, int s
     wave_lds_sync();
     float2 v[N];
     transform_frame<N, +1>(buf, v, lam);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<N>(acc, v);
     if (cur.valid() && cur.last()) snap_store<N>(a, f, cur.j, acc, lam);
     cur = nxt;
   }
@@ -377,7 +377,7 @@ __device__ __forceinline__ void image_item_pair_snap(const ImageArgs& a, int f, 
     SnapCursor nxt = cur;
     nxt.next();
     fetch_raw(nxt);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<N>(acc, v);
     if (cur.last()) snap_store<N>(a, f, cur.j, acc, lam);
     cur = nxt;
   }

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_image_acc(ImageAccArgs a) {
     static_for<0, N>([&](auto xc) { buf[lam * G::PITCH + decltype(xc)::value] = v[decltype(xc)::value]; });
     wave_lds_sync();
     transform_frame<N, +1>(buf, v, lam);
-    static_for<0, N>([&](auto yc) { acc[decltype(yc)::value] += cnorm(v[decltype(yc)::value]); });
+    add_norms<N>(acc, v);
     if (a.tap && active && lam == kx0) {
       float2 p = make_float2(0.f, 0.f);
       static_for<0, N>([&](auto yc) {

@@ -53,10 +53,10 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_SOURCES = ("k_image.hip", "image_fft.h", "image_cls.h", "engine.h", "fft_reg.h", "xpose.h", "epic_internal.h",
                    "epic_api.hip")
 TRAFFIC_MEASURED = {
-    "lwa": {"sources_sha256": "79f428c0d5fb28377bf5a80bd88dc3a2ce0a855c013bf858a2440f0fbe961146",
-            "fetch_kib": 173449.5, "fetch_scale": 2.000, "write_kib": 8192.0, "write_scale": 1.000},
-    "lwa_snapshot1": {"sources_sha256": "79f428c0d5fb28377bf5a80bd88dc3a2ce0a855c013bf858a2440f0fbe961146",
-                      "fetch_kib": 174335.2, "fetch_scale": 2.000, "write_kib": 20480097.9, "write_scale": 1.000},
+    "lwa": {"sources_sha256": "cf146e0725967256acff341d28546c9dbb3940fe1e8653b838f13ed1e69d1254",
+            "fetch_kib": 173447.7, "fetch_scale": 2.000, "write_kib": 8192.0, "write_scale": 1.000},
+    "lwa_snapshot1": {"sources_sha256": "cf146e0725967256acff341d28546c9dbb3940fe1e8653b838f13ed1e69d1254",
+                      "fetch_kib": 174325.0, "fetch_scale": 2.000, "write_kib": 20480115.3, "write_scale": 1.000},
 }
 
 
@@ -66,7 +66,7 @@ TRAFFIC_MEASURED = {
 # wave, two waves per SIMD, four cycles per instruction and wave) and the
 # fraction of the launch the LDS is busy (SQ_LDS_IDX_ACTIVE per CU).
 SQ_MEASURED = {
-    "lwa": {"sources_sha256": "79f428c0d5fb28377bf5a80bd88dc3a2ce0a855c013bf858a2440f0fbe961146", "valu_issue_frac": 0.59, "lds_busy_frac": 0.55},
+    "lwa": {"sources_sha256": "cf146e0725967256acff341d28546c9dbb3940fe1e8653b838f13ed1e69d1254", "valu_issue_frac": 0.58, "lds_busy_frac": 0.56},
 }
 
 

@@ -137,3 +137,24 @@ def test_several_pixels_above_512_antennas_run_separately(cuda):
     assert tim[lib.TIMER_SOLVE][1] == 1
     assert gain_err(got["hist"], ref["gains"]) <= GAIN_RTOL
     assert image_err(got["image"], ref["image"]).max() <= IMAGE_RTOL
+
+
+def test_fused_several_pixels_graph_replays(cuda):
+    """The fused several-pixel run captured in a hipGraph: replays with eager
+    work in between, each equal to the eager fused run (gains bit for bit)."""
+    import torch
+    from paper_1603_02126_amd import lib
+    wl = synth.config_small(n=64, efmt=synth.FMT_CI4, kernel=2, n_ant=200, n_chan=3, n_samples=160, t_cal=40)
+    packed = synth.make_efield(wl)
+    pix = wl.src_lmS[[0, 2, 5], :2]
+    eager, te = _run_pixels(wl, packed, pix, 1, cuda)
+    assert te[lib.TIMER_SOLVE][1] == 0
+    plan = _plan(wl, pix)
+    plan.set_option(lib.OPT_GRAPH, 1)
+    for rep in range(3):
+        got = gpu_run(wl, packed, cuda, plan=plan)
+        torch.randn(1000, device=cuda).sum()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got["hist"], eager["hist"])
+        assert image_err(got["image"], eager["image"]).max() <= 1e-6, rep
+    plan.close()
